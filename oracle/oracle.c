@@ -1,0 +1,185 @@
+/*
+ * oracle.c -- plain, slow, FP64 CPU oracle for the deskew of an oblique-plane
+ * light-sheet stack and its projections.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may call, link or
+ * load this file or the library built from it; only the test suite, the
+ * smoke check and the benchmark's CPU-baseline leg use it.  It shares no
+ * source with the HIP library: every formula below is written out from the
+ * paper's text (Lamb, Ward & Kaminski, arXiv 2211.00645).
+ *
+ * Notation (all indices are pixel centres, zero-based):
+ *   S[n][r][c]   raw stack, n = image (scan position), r = row, c = column;
+ *                the column axis is the one the sheet angle shears.
+ *   o[n]         lateral offset of image n in pixels ("Physical principles",
+ *                Eq. 1: l = z cos(alpha), divided by the sample-space pixel
+ *                size so the remap happens in image pixels).
+ *   b, W         origin and width of the larger image each raw image is
+ *                remapped into ("Physical principles", remap paragraph;
+ *                Fig. 2c).
+ *   D[n][r][x']  deskewed volume: image n placed at its accumulated lateral
+ *                shift, sampled with linear interpolation, zero outside the
+ *                raw image.
+ *   Psum, Pmax   sum and maximum over n of D (the maximum projection is the
+ *                mimicked widefield view, Fig. 2d; the sum is its linear
+ *                counterpart).
+ *
+ * Every value is computed in FP64 and rounded once to FP32 on output.
+ * Parallelism is one OpenMP loop over independent output rows; no blocking,
+ * fusion or reordering beyond that.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+
+/* Eq. 1: the lateral shift between consecutive images is l = z cos(alpha),
+ * z being the scan distance between images.  Expressed in image pixels of
+ * sample-space size p: s = (z * cos(alpha)) / p, alpha given in degrees. */
+double orc_shift_px(double angle_deg, double step_um, double pixel_um)
+{
+    double alpha = angle_deg * ORC_PI / 180.0;
+    return (step_um * cos(alpha)) / pixel_um;
+}
+
+/* Uniform scan: image n sits n scan steps away from image 0, so its
+ * accumulated offset is n times the per-step shift (Eq. 1 applied n times). */
+void orc_offsets_uniform(int64_t n_planes, double shift_px, double *offsets)
+{
+    for (int64_t n = 0; n < n_planes; ++n)
+        offsets[n] = (double)n * shift_px;
+}
+
+/* The larger image of the remap: it must hold every image at its offset.
+ * b is the leftmost integer column any image touches, W the number of
+ * columns from there to the rightmost column any image touches.  A column
+ * x' of the larger image corresponds to raw column x' + b - o[n]. */
+void orc_frame(int64_t n_planes, const double *offsets, int64_t cols,
+               int64_t *origin, int64_t *width)
+{
+    double lo = offsets[0], hi = offsets[0];
+    for (int64_t n = 1; n < n_planes; ++n) {
+        if (offsets[n] < lo) lo = offsets[n];
+        if (offsets[n] > hi) hi = offsets[n];
+    }
+    *origin = (int64_t)floor(lo);
+    *width = cols + (int64_t)ceil(hi) - *origin;
+}
+
+/* Raw sample with zero outside the image. */
+static double raw_at(const void *row, int is_f32, int64_t cols, int64_t i)
+{
+    if (i < 0 || i >= cols) return 0.0;
+    if (is_f32) return (double)((const float *)row)[i];
+    return (double)((const uint16_t *)row)[i];
+}
+
+/* Deskew by remapping (Physical principles, remap paragraph) plus the
+ * projections over the image axis (Fig. 2d).
+ *
+ * For every output column x' of image n the raw coordinate is
+ *     u = x' + b - o[n],  i = floor(u),  f = u - i,
+ * and the remapped value is the linear interpolation
+ *     D = (1 - f) * S~[i] + f * S~[i + 1],   S~ = 0 outside [0, cols).
+ * Psum = sum_n D and Pmax = max_n D over the dense D (padding included).
+ *
+ * Rows r in [r0, r1) are computed; outputs are laid out for that row range:
+ * vol/vol64 as [n_planes][r1 - r0][width], psum/pmax as [r1 - r0][width].
+ * Any output pointer may be NULL. */
+void orc_deskew(const void *stack, int is_f32, int64_t n_planes, int64_t rows,
+                int64_t cols, const double *offsets, int64_t origin,
+                int64_t width, int64_t r0, int64_t r1, float *vol,
+                double *vol64, float *psum, float *pmax)
+{
+    const int64_t nr = r1 - r0;
+    const size_t esz = is_f32 ? sizeof(float) : sizeof(uint16_t);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t rr = 0; rr < nr; ++rr) {
+        const int64_t r = r0 + rr;
+        double *sum = (double *)calloc((size_t)width, sizeof(double));
+        double *mx = (double *)malloc((size_t)width * sizeof(double));
+        for (int64_t x = 0; x < width; ++x) mx[x] = -INFINITY;
+        for (int64_t n = 0; n < n_planes; ++n) {
+            const char *row =
+                (const char *)stack + (size_t)((n * rows + r) * cols) * esz;
+            for (int64_t x = 0; x < width; ++x) {
+                double u = (double)x + (double)origin - offsets[n];
+                double fi = floor(u);
+                double f = u - fi;
+                int64_t i = (int64_t)fi;
+                double d = (1.0 - f) * raw_at(row, is_f32, cols, i) +
+                           f * raw_at(row, is_f32, cols, i + 1);
+                size_t o = (size_t)((n * nr + rr) * width + x);
+                if (vol) vol[o] = (float)d;
+                if (vol64) vol64[o] = d;
+                sum[x] += d;
+                if (d > mx[x]) mx[x] = d;
+            }
+        }
+        for (int64_t x = 0; x < width; ++x) {
+            if (psum) psum[rr * width + x] = (float)sum[x];
+            if (pmax) pmax[rr * width + x] = (float)mx[x];
+        }
+        free(sum);
+        free(mx);
+    }
+}
+
+/* Transpose of the remap, assembled explicitly as a scatter: every output
+ * voxel hands its gradient back to the two raw pixels it was interpolated
+ * from, with the same weights (1 - f) and f.  grad_in is [n_planes][rows]
+ * [cols]; grad_vol is the full [n_planes][rows][width] volume. */
+void orc_adjoint(const float *grad_vol, int64_t n_planes, int64_t rows,
+                 int64_t cols, const double *offsets, int64_t origin,
+                 int64_t width, float *grad_in, double *grad_in64)
+{
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t nr = 0; nr < n_planes * rows; ++nr) {
+        const int64_t n = nr / rows;
+        double *acc = (double *)calloc((size_t)cols, sizeof(double));
+        const float *g = grad_vol + (size_t)nr * (size_t)width;
+        for (int64_t x = 0; x < width; ++x) {
+            double u = (double)x + (double)origin - offsets[n];
+            double fi = floor(u);
+            double f = u - fi;
+            int64_t i = (int64_t)fi;
+            if (i >= 0 && i < cols) acc[i] += (1.0 - f) * (double)g[x];
+            if (i + 1 >= 0 && i + 1 < cols) acc[i + 1] += f * (double)g[x];
+        }
+        for (int64_t c = 0; c < cols; ++c) {
+            if (grad_in) grad_in[(size_t)nr * cols + c] = (float)acc[c];
+            if (grad_in64) grad_in64[(size_t)nr * cols + c] = acc[c];
+        }
+        free(acc);
+    }
+}
+
+/* Derivative of the loss with respect to each image's offset o[n].
+ * Inside a cell D = (1 - f) S~[i] + f S~[i + 1] with u = x' + b - o[n], so
+ * dD/do[n] = S~[j] - S~[j + 1].  The cell is taken as j = ceil(u) - 1, which
+ * is floor(u) away from integer u and, at integer u, the cell entered when
+ * o[n] grows: the right derivative in o[n].  grad_off[n] is the FP64 sum of
+ * grad_vol * dD/do[n] over all rows and output columns of image n. */
+void orc_shear_grad(const float *stack, const float *grad_vol,
+                    int64_t n_planes, int64_t rows, int64_t cols,
+                    const double *offsets, int64_t origin, int64_t width,
+                    double *grad_off)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t n = 0; n < n_planes; ++n) {
+        double acc = 0.0;
+        for (int64_t r = 0; r < rows; ++r) {
+            const float *row = stack + (size_t)((n * rows + r) * cols);
+            const float *g = grad_vol + (size_t)((n * rows + r) * width);
+            for (int64_t x = 0; x < width; ++x) {
+                double u = (double)x + (double)origin - offsets[n];
+                int64_t j = (int64_t)ceil(u) - 1;
+                double dd = raw_at(row, 1, cols, j) - raw_at(row, 1, cols, j + 1);
+                acc += (double)g[x] * dd;
+            }
+        }
+        grad_off[n] = acc;
+    }
+}

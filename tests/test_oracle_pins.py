@@ -1,0 +1,349 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these compares the oracle with itself: each checks it against a
+closed form, a library routine on a special case, an invariant of the
+interpolation, a hand-worked example, the paper's printed display geometry,
+or a brute-force dense operator built from the hat kernel.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_00645_amd import synth
+
+# ---------------------------------------------------------------- Eq. 1 --
+
+
+def test_eq1_closed_forms():
+    # l = z cos(alpha) (Eq. 1), in pixels of size p.
+    assert oracle.shift_px(0.0, 0.4, 0.115) == pytest.approx(0.4 / 0.115, rel=1e-15)
+    assert oracle.shift_px(60.0, 1.0, 1.0) == pytest.approx(0.5, abs=1e-15)
+    assert abs(oracle.shift_px(90.0, 1.0, 1.0)) < 1e-15
+    assert oracle.shift_px(30.0, 0.4, 0.115) == pytest.approx(
+        0.4 * math.sqrt(3.0) / 2.0 / 0.115, rel=1e-15)
+    assert oracle.shift_px(45.0, 0.4, 0.115) == pytest.approx(
+        0.4 * math.sqrt(2.0) / 2.0 / 0.115, rel=1e-15)
+    # scan direction reverses the shift
+    assert oracle.shift_px(30.0, -0.4, 0.115) == -oracle.shift_px(30.0, 0.4, 0.115)
+
+
+def test_uniform_offsets_and_frame():
+    o = oracle.offsets_uniform(5, 1.5)
+    assert list(o) == [0.0, 1.5, 3.0, 4.5, 6.0]
+    assert oracle.frame(o, 10) == (0, 16)
+    o = oracle.offsets_uniform(4, -0.75)          # negative scan step
+    assert oracle.frame(o, 10) == (-3, 13)
+    assert oracle.frame(np.array([0.0, 2.0, 4.0]), 7) == (0, 11)  # integer max
+
+
+# ------------------------------------------------- worked examples -------
+
+
+def test_hand_worked_example(golden):
+    g = golden("hand_worked_remap.txt")
+    s = np.array([[g["S0"]], [g["S1"]]], np.float32)
+    o = np.array(g["offsets"])
+    b, w = oracle.frame(o, 3)
+    assert (b, w) == (int(g["origin"][0]), int(g["width"][0]))
+    r = oracle.deskew(s, o)
+    np.testing.assert_array_equal(r["vol"][0, 0], np.array(g["D0"], np.float32))
+    np.testing.assert_array_equal(r["vol"][1, 0], np.array(g["D1"], np.float32))
+    np.testing.assert_array_equal(r["psum"][0], np.array(g["Psum"], np.float32))
+    np.testing.assert_array_equal(r["pmax"][0], np.array(g["Pmax"], np.float32))
+
+
+def test_paper_display_geometry(golden):
+    """The remap of the paper's 50-image, 87-px-wide region spans the 3652-px
+    display when the images are spread over it, and 3652 x 1304 px of 115 nm
+    are the paper's 420 x 150 um."""
+    g = golden("paper_display_geometry.txt")
+    n = int(g["images_per_stack"][0])
+    c = int(g["roi_sheared_px"][0])
+    disp = int(g["display_sheared_px"][0])
+    shift = (disp - c) / (n - 1)
+    b, w = oracle.frame(oracle.offsets_uniform(n, shift), c)
+    assert (b, w) == (0, disp)
+    p = g["pixel_um"][0]
+    assert abs(w * p - g["display_sheared_um"][0]) < 0.5      # paper rounds to um
+    assert abs(g["display_other_px"][0] * p - g["display_other_um"][0]) < 0.5
+    assert g["display_other_px"][0] == g["roi_other_px"][0]   # unsheared axis kept
+
+
+# ------------------------------------------------- special cases ---------
+
+
+@pytest.fixture(scope="module")
+def cfg1_stack():
+    return synth.blob_stack((64, 128, 256), 50, 0).numpy()
+
+
+def _slice_reference(s, k):
+    n, r, c = s.shape
+    w = c + int(max(k)) - int(min(0, min(k)))
+    b = int(min(0, min(k)))
+    out = np.zeros((n, r, w), np.float32)
+    for i in range(n):
+        out[i, :, k[i] - b:k[i] - b + c] = s[i]
+    return out, b, w
+
+
+@pytest.mark.parametrize("step", [3, -2, 0])
+def test_integer_shift_is_index_shift(cfg1_stack, step):
+    s = cfg1_stack
+    k = [step * i for i in range(s.shape[0])]
+    ref, b, w = _slice_reference(s, k)
+    r = oracle.deskew(s, np.array(k, np.float64))
+    assert (r["origin"], r["width"]) == (b, w)
+    assert r["vol"].tobytes() == ref.tobytes()
+    assert r["psum"].tobytes() == ref.astype(np.float64).sum(0).astype(np.float32).tobytes()
+    assert r["pmax"].tobytes() == ref.max(0).tobytes()
+
+
+def test_zero_shift_is_identity(cfg1_stack):
+    s = cfg1_stack
+    o = oracle.offsets_uniform(s.shape[0], oracle.shift_px(30.0, 0.0, 0.115))
+    r = oracle.deskew(s, o)
+    assert r["width"] == s.shape[2]
+    np.testing.assert_array_equal(r["vol"], s.astype(np.float32))
+    np.testing.assert_array_equal(r["pmax"], s.max(0).astype(np.float32))
+    np.testing.assert_array_equal(r["psum"], s.astype(np.float64).sum(0).astype(np.float32))
+
+
+# ------------------------------------------------- invariants ------------
+
+
+@pytest.fixture(scope="module")
+def cfg1_fractional(cfg1_stack):
+    o = oracle.offsets_uniform(64, oracle.shift_px(30.0, 0.4, 0.115))
+    return oracle.deskew(cfg1_stack, o, vol64=True), o
+
+
+def test_conservation(cfg1_stack, cfg1_fractional):
+    r, _ = cfg1_fractional
+    row_in = cfg1_stack.astype(np.float64).sum(2)
+    row_out = r["vol64"].sum(2)
+    np.testing.assert_allclose(row_out, row_in, rtol=1e-13)
+    assert float(r["psum"].astype(np.float64).sum()) == pytest.approx(
+        float(row_in.sum()), rel=1e-6)
+
+
+def test_first_and_second_moment(cfg1_stack, cfg1_fractional):
+    r, o = cfg1_fractional
+    s = cfg1_stack.astype(np.float64)
+    b = r["origin"]
+    c = np.arange(s.shape[2], dtype=np.float64)
+    xp = np.arange(r["width"], dtype=np.float64)
+    d = r["vol64"]
+    mass = s.sum(2)
+    m_in = (s * c).sum(2) / mass
+    m_out = (d * xp).sum(2) / mass
+    shift = (o - b)[:, None]
+    np.testing.assert_allclose(m_out, m_in + shift, rtol=0, atol=1e-9)
+    v_in = (s * (c[None, None, :] - m_in[:, :, None]) ** 2).sum(2) / mass
+    v_out = (d * (xp[None, None, :] - m_out[:, :, None]) ** 2).sum(2) / mass
+    phi = (o - b) - np.floor(o - b)
+    np.testing.assert_allclose(v_out - v_in, np.broadcast_to((phi * (1 - phi))[:, None], v_in.shape),
+                               rtol=0, atol=1e-8)
+
+
+def test_single_voxel_splits_in_two():
+    n, r, c = 3, 2, 12
+    s = np.zeros((n, r, c), np.float32)
+    s[2, 1, 5] = 1000.0
+    o = np.array([0.0, 1.3, 2.6])
+    out = oracle.deskew(s, o, vol64=True)
+    d = out["vol64"]
+    nz = np.argwhere(d != 0)
+    phi = 2.6 - 2.0
+    assert [tuple(v) for v in nz] == [(2, 1, 7), (2, 1, 8)]
+    assert d[2, 1, 7] == pytest.approx(1000.0 * (1 - phi), rel=1e-14)
+    assert d[2, 1, 8] == pytest.approx(1000.0 * phi, rel=1e-14)
+
+
+def test_point_source_lands_at_closed_form():
+    """A point at scan coordinate Y, height Z, lateral X, imaged on sheets at
+    alpha to the scan axis, must land at x' = (Y cos a + Z sin a)/p - b and
+    row X/p after the remap: the remap rotates the raw frame into the sheet
+    frame, viewed at (90 - alpha) degrees (Physical principles)."""
+    alpha, step, p = 30.0, 0.4, 0.115
+    a = math.radians(alpha)
+    n_pl, rows, cols = 50, 64, 128
+    y0, z0, x0, sig = 16.06, 3.5, 32 * 0.115, 0.5
+    n = np.arange(n_pl)[:, None, None]
+    rr = np.arange(rows)[None, :, None]
+    c = np.arange(cols)[None, None, :]
+    yy = n * step + c * p * math.cos(a)
+    zz = c * p * math.sin(a)
+    xx = rr * p
+    s = (1000.0 * np.exp(-((yy - y0) ** 2 + (zz - z0) ** 2 + (xx - x0) ** 2)
+                         / (2 * sig * sig))).astype(np.float32)
+    o = oracle.offsets_uniform(n_pl, oracle.shift_px(alpha, step, p))
+    out = oracle.deskew(s, o, vol64=True)
+    d = out["vol64"]
+    xp = np.arange(out["width"])
+    mass = d.sum()
+    x_c = (d.sum((0, 1)) * xp).sum() / mass
+    r_c = (d.sum((0, 2)) * np.arange(rows)).sum() / mass
+    assert x_c == pytest.approx((y0 * math.cos(a) + z0 * math.sin(a)) / p - out["origin"], abs=1e-6)
+    assert r_c == pytest.approx(x0 / p, abs=1e-6)
+    # the projections see the same centroid
+    ps = out["psum"].astype(np.float64)
+    assert (ps.sum(0) * xp).sum() / ps.sum() == pytest.approx(x_c, abs=1e-4)
+
+
+# ------------------------------------------------- brute force -----------
+
+
+def _dense_operator(o, b, w, n, r, c):
+    """Interpolation matrix from the hat kernel max(0, 1 - |x' + b - o_n - c|)."""
+    a = np.zeros((n * r * w, n * r * c))
+    for i in range(n):
+        for j in range(r):
+            for x in range(w):
+                for k in range(c):
+                    h = max(0.0, 1.0 - abs(x + b - o[i] - k))
+                    a[(i * r + j) * w + x, (i * r + j) * c + k] = h
+    return a
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_brute_force_dense(seed):
+    rng = np.random.default_rng(100 + seed)
+    n, r, c = int(rng.integers(1, 5)), int(rng.integers(1, 4)), int(rng.integers(2, 17))
+    o = rng.uniform(-4.0, 4.0, n)
+    if seed == 3:
+        o = np.round(o)          # integer offsets: pure index shifts
+    b, w = oracle.frame(o, c)
+    a = _dense_operator(o, b, w, n, r, c)
+    # W is the tight support: first and last output columns carry weight
+    cols_used = a.reshape(n * r, w, n * r * c).sum((0, 2))
+    assert cols_used[0] > 0 and cols_used[-1] > 0
+    s = rng.uniform(0, 100, (n, r, c)).astype(np.float32)
+    out = oracle.deskew(s, o, vol64=True)
+    np.testing.assert_allclose(out["vol64"].ravel(), a @ s.astype(np.float64).ravel(),
+                               rtol=0, atol=1e-11)
+    gd = rng.uniform(-1, 1, (n, r, w)).astype(np.float32)
+    gs = oracle.adjoint(gd, o, b, c, as_f64=True)
+    np.testing.assert_allclose(gs.ravel(), a.T @ gd.astype(np.float64).ravel(),
+                               rtol=0, atol=1e-11)
+    # d/do_n of the dense operator, one plane at a time (right derivative)
+    g = oracle.shear_grad(s, gd, o, b)
+    eps = 2.0 ** -20
+    for i in range(n):
+        o2 = o.copy()
+        o2[i] += eps
+        a2 = _dense_operator(o2, b, w, n, r, c)
+        dd = ((a2 - a) @ s.astype(np.float64).ravel()) / eps
+        assert g[i] == pytest.approx(float(gd.astype(np.float64).ravel() @ dd),
+                                     rel=1e-6, abs=1e-6)
+
+
+def test_clipped_and_padded_width(cfg1_stack):
+    o = oracle.offsets_uniform(64, oracle.shift_px(30.0, 0.4, 0.115))
+    full = oracle.deskew(cfg1_stack, o)
+    b, w = full["origin"], full["width"]
+    clip = oracle.deskew(cfg1_stack, o, origin=b, width=w - 37)
+    np.testing.assert_array_equal(clip["vol"], full["vol"][:, :, :w - 37])
+    pad = oracle.deskew(cfg1_stack, o, origin=b, width=w + 5)
+    np.testing.assert_array_equal(pad["vol"][:, :, :w], full["vol"])
+    assert not pad["vol"][:, :, w:].any()
+    rows = oracle.deskew(cfg1_stack, o, rows=(17, 23))
+    np.testing.assert_array_equal(rows["vol"], full["vol"][:, 17:23])
+    np.testing.assert_array_equal(rows["psum"], full["psum"][17:23])
+
+
+# ------------------------------------------------- adjoint / gradient ----
+
+
+def test_adjoint_dot_product():
+    rng = np.random.default_rng(7)
+    n, r, c = 16, 8, 64
+    o = oracle.offsets_uniform(n, 2.37)
+    b, w = oracle.frame(o, c)
+    x = rng.uniform(0, 1, (n, r, c)).astype(np.float32)
+    y = rng.uniform(0, 1, (n, r, w)).astype(np.float32)
+    ax = oracle.deskew(x, o, vol64=True)["vol64"]
+    aty = oracle.adjoint(y, o, b, c, as_f64=True)
+    lhs = float((ax * y.astype(np.float64)).sum())
+    rhs = float((x.astype(np.float64) * aty).sum())
+    assert abs(lhs - rhs) / (np.linalg.norm(ax) * np.linalg.norm(y)) < 1e-13
+
+
+def test_integer_adjoint_is_slice():
+    rng = np.random.default_rng(8)
+    n, r, c = 5, 3, 20
+    k = np.array([0, 2, 4, 6, 8])
+    b, w = oracle.frame(k.astype(np.float64), c)
+    gd = rng.uniform(-1, 1, (n, r, w)).astype(np.float32)
+    gs = oracle.adjoint(gd, k.astype(np.float64), b, c)
+    for i in range(n):
+        np.testing.assert_array_equal(gs[i], gd[i][:, k[i]:k[i] + c])
+
+
+def _plane_loss(s, o, b, w, gt, i):
+    d = oracle.deskew(s, o, origin=b, width=w, vol64=True)["vol64"]
+    return 0.5 * float(((d[i] - gt[i]) ** 2).sum())
+
+
+def test_shear_grad_matches_finite_differences():
+    """L = 1/2 |D(o) - G|^2 is piecewise quadratic in each o_n, so a central
+    difference inside one interpolation cell is exact up to rounding."""
+    s = synth.blob_stack((12, 10, 48), 8, 3, dtype="f32").numpy()
+    o = oracle.offsets_uniform(12, oracle.shift_px(30.0, 0.4, 0.115))
+    b, w = oracle.frame(o, 48)
+    o_gt = oracle.offsets_uniform(12, oracle.shift_px(32.0, 0.4, 0.115))
+    gt = oracle.deskew(s, o_gt, origin=b, width=w, vol64=True)["vol64"]
+    d = oracle.deskew(s, o, origin=b, width=w, vol64=True)["vol64"]
+    g = oracle.shear_grad(s, (d - gt).astype(np.float32), o, b)
+    h = 1e-3
+    checked = 0
+    for i in range(1, 12):
+        frac = (o[i] - b) - math.floor(o[i] - b)
+        if not (0.01 <= frac <= 0.99):
+            continue
+        op, om = o.copy(), o.copy()
+        op[i] += h
+        om[i] -= h
+        fd = (_plane_loss(s, op, b, w, gt, i) - _plane_loss(s, om, b, w, gt, i)) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-6, abs=1e-6 * np.abs(g).max())
+        checked += 1
+    assert checked >= 8
+
+
+def test_shear_grad_right_derivative_at_kink():
+    s = synth.blob_stack((6, 8, 40), 6, 5, dtype="f32").numpy()
+    o = np.array([0.0, 2.0, 4.0, 6.0, 8.0, 10.0])   # every plane at a kink
+    b, w = oracle.frame(o, 40)
+    rng = np.random.default_rng(9)
+    gt = rng.uniform(0, 500, (6, 8, w))
+    d = oracle.deskew(s, o, origin=b, width=w, vol64=True)["vol64"]
+    g = oracle.shear_grad(s, (d - gt).astype(np.float32), o, b)
+    h = 1e-3
+    for i in range(1, 6):
+        f = []
+        for m in range(3):
+            o2 = o.copy()
+            o2[i] += m * h
+            f.append(_plane_loss(s, o2, b, w, gt, i))
+        right = (-3 * f[0] + 4 * f[1] - f[2]) / (2 * h)   # exact for a quadratic
+        assert g[i] == pytest.approx(right, rel=1e-5)
+
+
+# ------------------------------------------------- generator -------------
+
+
+def test_generator_is_seeded_and_shaped():
+    a = synth.blob_stack((16, 64, 128), 5, 11).numpy()
+    b = synth.blob_stack((16, 64, 128), 5, 11).numpy()
+    c = synth.blob_stack((16, 64, 128), 5, 12).numpy()
+    assert a.dtype == np.uint16 and a.shape == (16, 64, 128)
+    assert np.array_equal(a, b) and not np.array_equal(a, c)
+    assert 95 <= np.median(a) <= 105             # Poisson(100) background
+    assert a.max() > 1000                        # blobs of amplitude >= 1000
+    jobs = synth.ragged_jobs(64, 0)
+    assert len(jobs) == 64
+    assert all(50 <= j["planes"] <= 400 and j["rows"] in (256, 512, 1024)
+               and 512 <= j["cols"] <= 2048 and j["angle_deg"] in (30.0, 35.0, 45.0)
+               and 0.2 <= j["step_um"] <= 0.8 for j in jobs)
