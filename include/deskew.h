@@ -1,0 +1,217 @@
+/*
+ * deskew.h -- C ABI of libdeskew.so: on-the-fly deskew of oblique-plane
+ * light-sheet stacks and their projections on an MI355X (gfx950).
+ *
+ * Method (Lamb, Ward & Kaminski, arXiv 2211.00645):
+ *   - Eq. 1: consecutive raw images are laterally offset by l = z cos(alpha),
+ *     z the scan distance between images and alpha the sheet angle.  In image
+ *     pixels of sample-space size p the per-image shift is
+ *         s = (z * cos(alpha * pi / 180)) / p          (FP64, this order)
+ *     and image n sits at offset o[n] = n * s (or caller-supplied offsets).
+ *   - "Physical principles", remap paragraph and Fig. 2c: each raw image is
+ *     remapped into a larger image at its accumulated offset.  The larger
+ *     image has origin b = floor(min o) and width W = C + ceil(max o) - b.
+ *     Output column x' of image n reads raw column x' + b - o[n] by linear
+ *     interpolation, zero outside the raw image.  With o[n] - b = k + phi
+ *     (k integer, phi in [0,1)):
+ *         D[n][r][x'] = (1 - phi) * S[n][r][x' - k] + phi * S[n][r][x' - k - 1]
+ *   - Fig. 2d: the maximum over images of D is the mimicked widefield view,
+ *         Pmax[r][x'] = max_n D[n][r][x'];  Psum[r][x'] = sum_n D[n][r][x']
+ *     (the sum accumulated in FP64, both rounded once to FP32).
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers owned by the caller unless a
+ *     parameter says "host".  Arrays are dense, C order:
+ *       stack  [planes][rows][cols]   (uint16 or float32)
+ *       vol    [planes][rows][width]  float32
+ *       psum, pmax [rows][width]      float32
+ *   - Kernels are enqueued on the caller's stream and the call returns
+ *     without waiting; nothing on the per-stack path allocates or
+ *     synchronises.
+ *   - Arguments are validated before anything is enqueued; on error nothing
+ *     is enqueued and a negative dsk_status is returned.  No C++ exception
+ *     crosses this boundary.
+ *   - Inputs must be finite (a non-finite neighbour with zero weight would
+ *     otherwise turn into NaN).  Device offsets must be finite.
+ *   - Outputs must not alias inputs.
+ */
+#ifndef DESKEW_H
+#define DESKEW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DSK_OK = 0,
+    DSK_EINVAL = -1,  /* null pointer, dims <= 0, non-finite geometry, pixel <= 0 */
+    DSK_ESHAPE = -2,  /* a size does not fit (index range, workspace too small) */
+    DSK_EHIP = -3,    /* HIP launch or runtime error */
+    DSK_ENOMEM = -4,  /* device or host allocation failed (batch objects only) */
+    DSK_EBUDGET = -5  /* request exceeds the serving memory budget */
+} dsk_status;
+
+typedef struct {
+    int32_t planes, rows, cols;
+} dsk_dims;
+
+/* alpha in degrees, scan step z in micrometres (negative reverses the scan),
+ * sample-space pixel size p in micrometres (> 0). */
+typedef struct {
+    double angle_deg, step_um, pixel_um;
+} dsk_geom;
+
+/* Launch shape of the forward kernels.  block: threads per workgroup (64,
+ * 128 or 256); per_thread: output columns per thread (1, 2, 4 or 8; 4 and 8
+ * use the aligned 16-byte vector kernel when the shape allows it);
+ * nt_store: 1 streams the volume with non-temporal stores; unroll: planes
+ * whose loads are issued together (1, 2 or 4); wg_per_cu: resident
+ * workgroups per compute unit for the persistent batch kernel (0 = as many
+ * as fit).  Every shape gives bitwise identical results. */
+typedef struct {
+    int32_t block, per_thread, nt_store, unroll, wg_per_cu;
+} dsk_tune;
+
+/* Human-readable name of a dsk_status value (static storage). */
+const char *dsk_status_string(int status);
+
+/* Per-image shift in pixels, Eq. 1: s = (z cos(alpha pi/180)) / p in FP64.
+ * shift_px: host out.  DSK_EINVAL if a value is non-finite or p <= 0. */
+int dsk_shift_px(dsk_geom g, double *shift_px);
+
+/* Shape query for the remap's larger image ("Physical principles", remap
+ * paragraph).  offsets_px: host array of d.planes offsets, or NULL for the
+ * uniform scan o[n] = n * shift_px.  Writes W to *out_width and b to
+ * *origin (host).  Host only; touches no device.  DSK_ESHAPE if W reaches
+ * 2^30 (widths and column counts stay below 2^30 everywhere). */
+int dsk_plan(dsk_dims d, const double *offsets_px, double shift_px,
+             int64_t *out_width, int64_t *origin);
+
+/* Deskew a uint16 stack scanned uniformly with geometry g: o[n] = n * s,
+ * origin and width from dsk_plan.  out_width 0 selects W; a positive value
+ * clips or zero-pads the grid on the same formula.  vol, psum and pmax may
+ * each be NULL (vol NULL is the live-view case); at least one must be set.
+ * One fused pass: the volume and both projections come from one read of the
+ * stack. */
+int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float *vol,
+                   float *psum, float *pmax, int64_t out_width,
+                   hipStream_t stream);
+
+/* As dsk_deskew_u16 with explicit per-image offsets (pixels).  offsets_dev:
+ * DEVICE array of d.planes FP64 offsets (scan jitter, autograd).  origin
+ * (b) and out_width (> 0) are explicit, so the grid can stay fixed while
+ * the offsets change. */
+int dsk_deskew_offsets_u16(const uint16_t *in, dsk_dims d,
+                           const double *offsets_dev, int64_t origin,
+                           float *vol, float *psum, float *pmax,
+                           int64_t out_width, hipStream_t stream);
+
+/* Float32 input, same contract as dsk_deskew_offsets_u16. */
+int dsk_deskew_offsets_f32(const float *in, dsk_dims d,
+                           const double *offsets_dev, int64_t origin,
+                           float *vol, float *psum, float *pmax,
+                           int64_t out_width, hipStream_t stream);
+
+/* Forward with an explicit launch shape (tune != NULL) -- used by the
+ * autotuner and the benchmark; results are bitwise identical for every
+ * shape.  in_is_f32 selects the input type (in points to uint16 or float). */
+int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
+                             const double *offsets_dev, double shift_px,
+                             int64_t origin, float *vol, float *psum,
+                             float *pmax, int64_t out_width,
+                             const dsk_tune *tune, hipStream_t stream);
+
+/* Adjoint of the remap (its transpose) applied to grad_vol [planes][rows]
+ * [out_width], written as a gather with no atomics:
+ *   grad_in[n][r][c] = (1-phi) gD[n][r][c+k] + phi gD[n][r][c+k+1],
+ * gD read as 0 outside [0, out_width).  grad_in: [planes][rows][cols]. */
+int dsk_deskew_adjoint_f32(const float *grad_vol, dsk_dims d,
+                           const double *offsets_dev, int64_t origin,
+                           int64_t out_width, float *grad_in,
+                           hipStream_t stream);
+
+/* Bytes of device workspace dsk_shear_grad_f32 / dsk_backward_f32 need. */
+size_t dsk_shear_grad_workspace_bytes(dsk_dims d);
+
+/* Derivative of a loss with respect to each image offset, given
+ * grad_vol = dLoss/dD and the float32 stack in:
+ *   grad_offsets[n] = sum_{r,x'} gD[n][r][x'] (S[x'-k-1] - S[x'-k])
+ * (the right derivative in o[n] where o[n] - b is an integer), summed in
+ * FP64 in a fixed order (deterministic).  grad_offsets: DEVICE, planes
+ * doubles.  workspace: DEVICE, at least dsk_shear_grad_workspace_bytes(d)
+ * bytes, caller-owned, contents need not be initialised. */
+int dsk_shear_grad_f32(const float *in, const float *grad_vol, dsk_dims d,
+                       const double *offsets_dev, int64_t origin,
+                       int64_t out_width, double *grad_offsets,
+                       void *workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+
+/* Fused backward: grad_in (adjoint) and grad_offsets (shear gradient) from
+ * one read of grad_vol.  Either output may be NULL (not both); the
+ * workspace is required when grad_offsets is set. */
+int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims d,
+                     const double *offsets_dev, int64_t origin,
+                     int64_t out_width, float *grad_in, double *grad_offsets,
+                     void *workspace, size_t workspace_bytes,
+                     hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * Ragged batches: many uint16 stacks of different sizes and geometries in
+ * one persistent launch (one workgroup per compute-unit slot walks a shared
+ * list of (stack, row, column-tile) items).  Each job's outputs are bitwise
+ * identical to its own dsk_deskew_offsets_u16 / dsk_deskew_u16 call.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    const uint16_t *in;         /* device stack [planes][rows][cols] */
+    dsk_dims dims;
+    const double *offsets_dev;  /* device offsets, or NULL: o[n] = n*shift_px */
+    double shift_px;
+    int64_t origin;             /* b */
+    int64_t out_width;          /* W (> 0) */
+    float *vol, *psum, *pmax;   /* device outputs, each may be NULL */
+} dsk_job;
+
+typedef struct dsk_batch dsk_batch;
+
+/* Build a batch: validates the jobs, uploads the job table (device memory
+ * owned by the batch), picks the launch shape (tune != NULL: use it; NULL:
+ * time the candidate shapes on `stream`, which runs the jobs -- outputs are
+ * then already written), and captures the launch in a HIP graph.  Host
+ * call; allocates and synchronises `stream`. */
+int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune *tune,
+                     hipStream_t stream, dsk_batch **out);
+
+/* Replay the captured graph on `stream` (asynchronous). */
+int dsk_batch_launch(dsk_batch *batch, hipStream_t stream);
+
+/* Launch the persistent kernel directly, without the graph. */
+int dsk_batch_launch_direct(dsk_batch *batch, hipStream_t stream);
+
+/* The launch shape the batch uses, and the autotuner's best time (ms, 0
+ * when the shape was given). */
+int dsk_batch_get_tune(const dsk_batch *batch, dsk_tune *tune, double *ms);
+
+int dsk_batch_destroy(dsk_batch *batch);
+
+/* Bytes of device job table dsk_jobs_launch needs for n_jobs jobs. */
+size_t dsk_jobs_table_bytes(int n_jobs);
+
+/* One persistent launch over jobs given per call (the serving path).
+ * table_host: host buffer of dsk_jobs_table_bytes(n_jobs) bytes, ideally
+ * pinned; it is encoded here and copied to table_dev with hipMemcpyAsync on
+ * `stream`, so it must stay unchanged until that copy completes (record an
+ * event).  table_dev: device buffer of the same size.  tune may be NULL. */
+int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host,
+                    void *table_dev, size_t table_bytes, const dsk_tune *tune,
+                    hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DESKEW_H */

@@ -36,6 +36,8 @@ def _load():
         from . import build as _b
         _b.build()
     lib = ctypes.CDLL(_LIB_PATH)
+    lib.orc_threads.restype = ctypes.c_int
+    lib.orc_threads.argtypes = []
     lib.orc_shift_px.restype = ctypes.c_double
     lib.orc_shift_px.argtypes = [ctypes.c_double] * 3
     lib.orc_offsets_uniform.restype = None
@@ -61,6 +63,11 @@ def _ptr(a, typ):
     if a is None:
         return None
     return a.ctypes.data_as(typ)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(_load().orc_threads())
 
 
 def shift_px(angle_deg: float, step_um: float, pixel_um: float) -> float:

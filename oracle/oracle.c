@@ -32,8 +32,21 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_PI 3.14159265358979323846
+
+/* Threads the parallel loops below use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Eq. 1: the lateral shift between consecutive images is l = z cos(alpha),
  * z being the scan distance between images.  Expressed in image pixels of

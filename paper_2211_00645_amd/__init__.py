@@ -1,0 +1,11 @@
+"""MI355X-native deskew of oblique-plane light-sheet stacks (arXiv 2211.00645).
+
+The hot path -- remap of every raw image to its lateral offset (Eq. 1) with
+fused sum and maximum projections, its adjoint and shear gradient, ragged
+batches and the live serving loop -- runs in the HIP kernels of
+``libdeskew.so`` (C ABI in ``include/deskew.h``).  Import is light: the
+library is loaded on first use and its absence is an error, never a fallback.
+"""
+from .api import adjoint, backward, deskew, plan, shear_grad, shift_px  # noqa: F401
+
+__all__ = ["deskew", "plan", "shift_px", "backward", "adjoint", "shear_grad"]

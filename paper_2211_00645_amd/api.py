@@ -1,0 +1,210 @@
+"""Torch-facing API over libdeskew.so.
+
+PyTorch provides device memory and the current stream; the deskew itself runs
+in the library's kernels.  Stacks are [planes][rows][cols] CUDA tensors
+(uint16 or float32, contiguous); outputs are float32 CUDA tensors:
+``vol`` [planes][rows][width], ``psum`` and ``pmax`` [rows][width].
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _vp(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dims(shape):
+    n, r, c = (int(v) for v in shape)
+    return L.Dims(n, r, c)
+
+
+def _check_stack(x, dtypes=(torch.uint16, torch.float32)):
+    if not isinstance(x, torch.Tensor) or x.dim() != 3:
+        raise ValueError("stack must be a 3-D tensor [planes][rows][cols]")
+    if not x.is_cuda:
+        raise ValueError("stack must be a CUDA (HIP) tensor")
+    if x.dtype not in dtypes:
+        raise TypeError(f"stack dtype {x.dtype} not in {dtypes}")
+    if not x.is_contiguous():
+        raise ValueError("stack must be contiguous")
+
+
+def _tune(t):
+    if t is None:
+        return None
+    if isinstance(t, L.Tune):
+        return t
+    return L.Tune(int(t.get("block", 256)), int(t.get("per_thread", 4)),
+                  int(t.get("nt_store", 0)), int(t.get("unroll", 2)),
+                  int(t.get("wg_per_cu", 0)))
+
+
+def shift_px(angle_deg: float, step_um: float, pixel_um: float) -> float:
+    """Per-image shift in pixels (Eq. 1), computed by the library in FP64."""
+    out = ctypes.c_double()
+    L.check(L.lib().dsk_shift_px(L.Geom(angle_deg, step_um, pixel_um), ctypes.byref(out)),
+            "dsk_shift_px")
+    return out.value
+
+
+def plan(shape, shift=None, offsets=None):
+    """(width W, origin b) of the remap's larger image for a stack shape."""
+    w, b = ctypes.c_int64(), ctypes.c_int64()
+    if offsets is not None:
+        o = np.ascontiguousarray(
+            offsets.detach().cpu().numpy() if isinstance(offsets, torch.Tensor) else offsets,
+            np.float64)
+        if o.shape != (int(shape[0]),):
+            raise ValueError("offsets must have one entry per plane")
+        ptr = o.ctypes.data_as(ctypes.c_void_p)
+        st = L.lib().dsk_plan(_dims(shape), ptr, 0.0, ctypes.byref(w), ctypes.byref(b))
+    else:
+        st = L.lib().dsk_plan(_dims(shape), None, float(shift), ctypes.byref(w), ctypes.byref(b))
+    L.check(st, "dsk_plan")
+    return int(w.value), int(b.value)
+
+
+def _offsets_dev(offsets, device):
+    if isinstance(offsets, torch.Tensor):
+        o = offsets.detach().to(device=device, dtype=torch.float64).contiguous()
+    else:
+        o = torch.as_tensor(np.asarray(offsets, np.float64), device=device)
+    return o
+
+
+def deskew(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
+           offsets=None, origin=None, width=None, vol=True, psum=True, pmax=True,
+           out=None, tune=None, stream=None):
+    """Deskew ``stack`` and project it (one fused pass).
+
+    Geometry is either (angle_deg, step_um, pixel_um) for a uniform scan, or
+    explicit per-plane ``offsets`` in pixels.  ``origin``/``width`` default
+    to the full frame.  ``out`` may hold preallocated ``vol``/``psum``/
+    ``pmax`` tensors.  Returns a dict with the outputs, ``origin`` and
+    ``width``.
+    """
+    _check_stack(stack)
+    dev = stack.device
+    shape = tuple(stack.shape)
+    shift = None
+    if offsets is None:
+        if None in (angle_deg, step_um, pixel_um):
+            raise ValueError("give angle_deg, step_um and pixel_um, or offsets")
+        shift = shift_px(angle_deg, step_um, pixel_um)
+        w0, b0 = plan(shape, shift=shift)
+    else:
+        w0, b0 = (None, None) if (origin is not None and width is not None) else plan(
+            shape, offsets=offsets)
+    origin = b0 if origin is None else int(origin)
+    width = w0 if width is None else int(width)
+    n, r, _ = shape
+    out = dict(out or {})
+    res = {"origin": origin, "width": width}
+    for key, want, shp in (("vol", vol, (n, r, width)), ("psum", psum, (r, width)),
+                           ("pmax", pmax, (r, width))):
+        if not want:
+            continue
+        t = out.get(key)
+        if t is None:
+            t = torch.empty(shp, dtype=torch.float32, device=dev)
+        elif t.shape != shp or t.dtype != torch.float32 or not t.is_contiguous() or t.device != dev:
+            raise ValueError(f"out[{key!r}] must be contiguous float32 {shp} on {dev}")
+        res[key] = t
+    v, ps, pm = res.get("vol"), res.get("psum"), res.get("pmax")
+    lib = L.lib()
+    s = _stream(stream)
+    tn = _tune(tune)
+    is_f32 = stack.dtype == torch.float32
+    if offsets is None and tn is None and not is_f32 and width == w0:
+        st = lib.dsk_deskew_u16(_vp(stack), _dims(shape), L.Geom(angle_deg, step_um, pixel_um),
+                                _vp(v), _vp(ps), _vp(pm), 0, s)
+        L.check(st, "dsk_deskew_u16")
+        return res
+    od = None if offsets is None else _offsets_dev(offsets, dev)
+    res["_offsets_dev"] = od          # keep alive until the kernel has read it
+    if tn is not None or od is None:
+        st = lib.dsk_deskew_offsets_tuned(_vp(stack), int(is_f32), _dims(shape), _vp(od),
+                                          float(shift or 0.0), origin, _vp(v), _vp(ps), _vp(pm),
+                                          width, ctypes.byref(tn) if tn is not None else None, s)
+        L.check(st, "dsk_deskew_offsets_tuned")
+    elif is_f32:
+        st = lib.dsk_deskew_offsets_f32(_vp(stack), _dims(shape), _vp(od), origin, _vp(v),
+                                        _vp(ps), _vp(pm), width, s)
+        L.check(st, "dsk_deskew_offsets_f32")
+    else:
+        st = lib.dsk_deskew_offsets_u16(_vp(stack), _dims(shape), _vp(od), origin, _vp(v),
+                                        _vp(ps), _vp(pm), width, s)
+        L.check(st, "dsk_deskew_offsets_u16")
+    return res
+
+
+def backward(stack, grad_vol, offsets_dev, origin, *, grad_in=True, grad_offsets=True,
+             stream=None):
+    """Adjoint (grad wrt the float32 stack) and/or per-plane shear gradient.
+
+    ``offsets_dev`` is a float64 CUDA tensor; ``grad_vol`` is float32
+    [planes][rows][width].  Returns (grad_in or None, grad_offsets or None).
+    """
+    _check_stack(grad_vol, (torch.float32,))
+    _check_stack(stack, (torch.float32,))
+    n, r, w = grad_vol.shape
+    if stack.shape[:2] != grad_vol.shape[:2]:
+        raise ValueError("stack and grad_vol disagree in planes/rows")
+    c = stack.shape[2]
+    if offsets_dev.dtype != torch.float64 or not offsets_dev.is_cuda or offsets_dev.numel() != n:
+        raise ValueError("offsets_dev must be a float64 CUDA tensor with one entry per plane")
+    offsets_dev = offsets_dev.contiguous()
+    dev = grad_vol.device
+    dims = L.Dims(n, r, c)
+    gi = torch.empty((n, r, c), dtype=torch.float32, device=dev) if grad_in else None
+    go = torch.empty((n,), dtype=torch.float64, device=dev) if grad_offsets else None
+    lib = L.lib()
+    ws = None
+    wsb = 0
+    if grad_offsets:
+        wsb = int(lib.dsk_shear_grad_workspace_bytes(dims))
+        ws = torch.empty((max(1, wsb // 8),), dtype=torch.float64, device=dev)
+    st = lib.dsk_backward_f32(_vp(stack), _vp(grad_vol), dims, _vp(offsets_dev), int(origin),
+                              int(w), _vp(gi), _vp(go), _vp(ws), wsb, _stream(stream))
+    L.check(st, "dsk_backward_f32")
+    return gi, go
+
+
+def adjoint(grad_vol, offsets_dev, origin, cols, stream=None):
+    """Transpose of the remap: grad_vol [N][R][W] -> [N][R][cols]."""
+    _check_stack(grad_vol, (torch.float32,))
+    n, r, w = grad_vol.shape
+    dims = L.Dims(n, r, int(cols))
+    gi = torch.empty((n, r, int(cols)), dtype=torch.float32, device=grad_vol.device)
+    st = L.lib().dsk_deskew_adjoint_f32(_vp(grad_vol), dims, _vp(offsets_dev.contiguous()),
+                                        int(origin), int(w), _vp(gi), _stream(stream))
+    L.check(st, "dsk_deskew_adjoint_f32")
+    return gi
+
+
+def shear_grad(stack, grad_vol, offsets_dev, origin, stream=None):
+    """Per-plane d(loss)/d(offset) in FP64 given d(loss)/dD."""
+    _check_stack(stack, (torch.float32,))
+    _check_stack(grad_vol, (torch.float32,))
+    n, r, c = stack.shape
+    w = grad_vol.shape[2]
+    dims = L.Dims(n, r, c)
+    lib = L.lib()
+    wsb = int(lib.dsk_shear_grad_workspace_bytes(dims))
+    ws = torch.empty((max(1, wsb // 8),), dtype=torch.float64, device=stack.device)
+    go = torch.empty((n,), dtype=torch.float64, device=stack.device)
+    st = lib.dsk_shear_grad_f32(_vp(stack), _vp(grad_vol), dims, _vp(offsets_dev.contiguous()),
+                                int(origin), int(w), _vp(go), _vp(ws), wsb, _stream(stream))
+    L.check(st, "dsk_shear_grad_f32")
+    return go

@@ -1,0 +1,373 @@
+// batch.hip -- ragged batches of uint16 stacks in one persistent launch:
+// device job table, launch-shape autotuner with an on-disk cache, and HIP
+// graph capture of the launch.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "deskew.h"
+#include "kernels.hpp"
+
+using namespace dsk;
+
+struct dsk_batch {
+    int device = 0;
+    int n_jobs = 0;
+    std::vector<dsk_job> jobs;
+    dsk_tune tune{};
+    double best_ms = 0.0;
+    int64_t total_tiles = 0;
+    int grid = 0;
+    JobDev *table_dev = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+using JobsKernel = void (*)(const JobDev *, int, int64_t);
+
+JobsKernel pick_kernel(const dsk_tune &t) {
+    return dispatch_tune(t, [](auto B, auto P, auto U, auto NT) -> JobsKernel {
+        return k_forward_jobs<decltype(B)::value, decltype(P)::value, decltype(U)::value,
+                              decltype(NT)::value>;
+    });
+}
+
+int validate_job(const dsk_job &j) {
+    if (!j.in || !dims_ok(j.dims) || (!j.vol && !j.psum && !j.pmax)) return DSK_EINVAL;
+    if (!j.offsets_dev && !std::isfinite(j.shift_px)) return DSK_EINVAL;
+    return check_frame(j.dims, j.origin, j.out_width);
+}
+
+// Job table for a launch shape; returns the total tile count (or < 0).
+int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out) {
+    int64_t begin = 0;
+    for (int i = 0; i < n; ++i) {
+        const dsk_job &j = jobs[i];
+        const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol);
+        const int64_t tx = tiles_x(j.out_width, t, vec);
+        if (tx > kMaxI32) return -1;
+        JobDev r;
+        r.in = j.in;
+        r.vol = j.vol;
+        r.psum = j.psum;
+        r.pmax = j.pmax;
+        r.offs = j.offsets_dev;
+        r.shift = j.shift_px;
+        r.origin = (double)j.origin;
+        r.W = j.out_width;
+        r.tile_begin = begin;
+        r.N = j.dims.planes;
+        r.R = j.dims.rows;
+        r.C = j.dims.cols;
+        r.tiles_x = (int32_t)tx;
+        r.vec = vec ? 1 : 0;
+        r.pad_ = 0;
+        out[i] = r;
+        begin += tx * j.dims.rows;
+        if (begin < 0 || begin > (int64_t(1) << 50)) return -1;
+    }
+    return begin;
+}
+
+// Resident workgroups for the persistent grid.
+int persistent_grid(const dsk_tune &t, int64_t total_tiles) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return -1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick_kernel(t),
+                                                     t.block, 0) != hipSuccess)
+        return -1;
+    if (per_cu < 1) per_cu = 1;
+    if (t.wg_per_cu > 0 && t.wg_per_cu < per_cu) per_cu = t.wg_per_cu;
+    int64_t g = (int64_t)cus * per_cu;
+    if (g > total_tiles) g = total_tiles;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+hipError_t launch_jobs(const JobDev *table, int n, int64_t total, int grid, const dsk_tune &t,
+                       hipStream_t s) {
+    void *args[] = {(void *)&table, (void *)&n, (void *)&total};
+    return hipLaunchKernel((const void *)pick_kernel(t), dim3(grid), dim3(t.block), args, 0, s);
+}
+
+// ---- tuned-shape cache (JSON object, one entry per line) -----------------
+
+std::mutex g_cache_mu;
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return "unknown";
+    std::string a(p.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+int log2_bucket(double v) { return v <= 1.0 ? 0 : (int)std::floor(std::log2(v)); }
+
+// Shape class: arch, job count, and log2 buckets of total output voxels
+// and mean planes per job.
+std::string shape_key(const dsk_job *jobs, int n) {
+    double vox = 0.0, planes = 0.0;
+    for (int i = 0; i < n; ++i) {
+        vox += (double)jobs[i].dims.planes * jobs[i].dims.rows * (double)jobs[i].out_width;
+        planes += jobs[i].dims.planes;
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s/jobs%d/vox2^%d/planes2^%d", arch_name().c_str(), n,
+                  log2_bucket(vox), log2_bucket(planes / n));
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, dsk_tune *t, double *ms) {
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        dsk_tune c{};
+        double m = 0.0;
+        if (std::sscanf(line,
+                        " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
+                        "\"unroll\": %d, \"wg_per_cu\": %d, \"ms\": %lf}",
+                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu,
+                        &m) == 7 &&
+            key == k && tune_ok(c)) {
+            *t = c;
+            *ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const dsk_tune &t, double ms) {
+    // Keep every other entry, replace this key, rewrite the file.
+    std::vector<std::string> keep;
+    if (std::FILE *f = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+            char k[256];
+            if (std::sscanf(line, " \"%255[^\"]\":", k) == 1 && key != k) {
+                std::string s(line);
+                while (!s.empty() && (s.back() == '\n' || s.back() == ',')) s.pop_back();
+                keep.push_back(s);
+            }
+        }
+        std::fclose(f);
+    }
+    char ent[512];
+    std::snprintf(ent, sizeof ent,
+                  "  \"%s\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
+                  "\"unroll\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}",
+                  key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu, ms);
+    keep.push_back(ent);
+    const std::string tmp = std::string(path) + ".tmp";
+    std::FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < keep.size(); ++i)
+        std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    std::fputs("}\n", f);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+// Launch shapes the autotuner times.
+std::vector<dsk_tune> candidates() {
+    std::vector<dsk_tune> c;
+    for (int b : {128, 256})
+        for (int j : {4, 8})
+            for (int u : {1, 2})
+                for (int nt : {0, 1}) c.push_back(dsk_tune{b, j, nt, u, 0});
+    return c;
+}
+
+int upload_table(dsk_batch *bt, const dsk_tune &t, hipStream_t s) {
+    std::vector<JobDev> host((size_t)bt->n_jobs);
+    const int64_t total = encode_table(bt->jobs.data(), bt->n_jobs, t, host.data());
+    if (total <= 0) return DSK_ESHAPE;
+    hipError_t e = hipMemcpyAsync(bt->table_dev, host.data(), host.size() * sizeof(JobDev),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return DSK_EHIP;
+    bt->total_tiles = total;
+    bt->grid = persistent_grid(t, total);
+    return bt->grid > 0 ? DSK_OK : DSK_EHIP;
+}
+
+// Best of `reps` timed launches (ms) of shape t.
+int time_shape(dsk_batch *bt, const dsk_tune &t, hipStream_t s, int reps, double *ms) {
+    int st = upload_table(bt, t, s);
+    if (st != DSK_OK) return st;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return DSK_EHIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return DSK_EHIP;
+    }
+    double best = 1e300;
+    hipError_t e = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, t, s);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) {
+        e = hipEventRecord(a, s);
+        if (e == hipSuccess) e = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, t, s);
+        if (e == hipSuccess) e = hipEventRecord(b, s);
+        if (e == hipSuccess) e = hipEventSynchronize(b);
+        float f = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+        if (e == hipSuccess && f < best) best = f;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (e != hipSuccess) return DSK_EHIP;
+    *ms = best;
+    return DSK_OK;
+}
+
+}  // namespace
+
+extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune *tune,
+                                hipStream_t stream, dsk_batch **out) {
+    if (!out || !jobs || n_jobs <= 0) return DSK_EINVAL;
+    *out = nullptr;
+    if (tune && !tune_ok(*tune)) return DSK_EINVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const int st = validate_job(jobs[i]);
+        if (st != DSK_OK) return st;
+    }
+    dsk_batch *bt = new (std::nothrow) dsk_batch;
+    if (!bt) return DSK_ENOMEM;
+    bt->n_jobs = n_jobs;
+    bt->jobs.assign(jobs, jobs + n_jobs);
+    if (hipGetDevice(&bt->device) != hipSuccess) {
+        delete bt;
+        return DSK_EHIP;
+    }
+    if (hipMalloc((void **)&bt->table_dev, sizeof(JobDev) * (size_t)n_jobs) != hipSuccess) {
+        delete bt;
+        return DSK_ENOMEM;
+    }
+    int st = DSK_OK;
+    if (tune) {
+        bt->tune = *tune;
+        bt->best_ms = 0.0;
+    } else {
+        const char *path = std::getenv("DSK_TUNE_CACHE");
+        const std::string key = shape_key(jobs, n_jobs);
+        dsk_tune t{};
+        double ms = 0.0;
+        bool hit = false;
+        if (path && *path) {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            hit = cache_lookup(path, key, &t, &ms);
+        }
+        if (!hit) {
+            double best = 1e300;
+            for (const dsk_tune &c : candidates()) {
+                double m = 0.0;
+                st = time_shape(bt, c, stream, 2, &m);
+                if (st != DSK_OK) break;
+                if (m < best) {
+                    best = m;
+                    t = c;
+                }
+            }
+            ms = best;
+            if (st == DSK_OK && path && *path) {
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                cache_store(path, key, t, ms);
+            }
+        }
+        bt->tune = t;
+        bt->best_ms = ms;
+    }
+    if (st == DSK_OK) st = upload_table(bt, bt->tune, stream);
+    if (st == DSK_OK) {
+        // Capture the persistent launch on a private stream.
+        hipStream_t cap = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid,
+                                        bt->tune, cap);
+            e = hipStreamEndCapture(cap, &bt->graph);
+            if (le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0);
+        if (cap) (void)hipStreamDestroy(cap);
+        if (e != hipSuccess) st = DSK_EHIP;
+    }
+    if (st != DSK_OK) {
+        dsk_batch_destroy(bt);
+        return st;
+    }
+    *out = bt;
+    return DSK_OK;
+}
+
+extern "C" int dsk_batch_launch(dsk_batch *bt, hipStream_t stream) {
+    if (!bt || !bt->exec) return DSK_EINVAL;
+    return hip_status(hipGraphLaunch(bt->exec, stream));
+}
+
+extern "C" int dsk_batch_launch_direct(dsk_batch *bt, hipStream_t stream) {
+    if (!bt || !bt->table_dev) return DSK_EINVAL;
+    return hip_status(
+        launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, bt->tune, stream));
+}
+
+extern "C" int dsk_batch_get_tune(const dsk_batch *bt, dsk_tune *tune, double *ms) {
+    if (!bt) return DSK_EINVAL;
+    if (tune) *tune = bt->tune;
+    if (ms) *ms = bt->best_ms;
+    return DSK_OK;
+}
+
+extern "C" int dsk_batch_destroy(dsk_batch *bt) {
+    if (!bt) return DSK_EINVAL;
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    if (bt->table_dev) (void)hipFree(bt->table_dev);
+    delete bt;
+    return DSK_OK;
+}
+
+extern "C" size_t dsk_jobs_table_bytes(int n_jobs) {
+    return n_jobs > 0 ? sizeof(JobDev) * (size_t)n_jobs : 0;
+}
+
+extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host,
+                               void *table_dev, size_t table_bytes, const dsk_tune *tune,
+                               hipStream_t stream) {
+    if (!jobs || n_jobs <= 0 || !table_host || !table_dev) return DSK_EINVAL;
+    if (table_bytes < dsk_jobs_table_bytes(n_jobs)) return DSK_ESHAPE;
+    const dsk_tune t = tune ? *tune : kDefaultTune;
+    if (!tune_ok(t)) return DSK_EINVAL;
+    for (int i = 0; i < n_jobs; ++i) {
+        const int st = validate_job(jobs[i]);
+        if (st != DSK_OK) return st;
+    }
+    JobDev *host = (JobDev *)table_host;
+    const int64_t total = encode_table(jobs, n_jobs, t, host);
+    if (total <= 0) return DSK_ESHAPE;
+    const int grid = persistent_grid(t, total);
+    if (grid <= 0) return DSK_EHIP;
+    hipError_t e = hipMemcpyAsync(table_dev, host, dsk_jobs_table_bytes(n_jobs),
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = launch_jobs((const JobDev *)table_dev, n_jobs, total, grid, t, stream);
+    return hip_status(e);
+}

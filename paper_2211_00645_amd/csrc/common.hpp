@@ -1,0 +1,99 @@
+// common.hpp -- host-side helpers shared by the translation units of
+// libdeskew.so (validation, launch-shape checks, HIP error mapping).
+#pragma once
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+#include "deskew.h"
+
+namespace dsk {
+
+constexpr int64_t kMaxI32 = 2147483647;
+
+// Default forward launch shape.
+constexpr dsk_tune kDefaultTune = {256, 4, 0, 2, 0};
+
+inline bool dims_ok(dsk_dims d) {
+    return d.planes > 0 && d.rows > 0 && d.cols > 0;
+}
+
+inline bool tune_ok(const dsk_tune &t) {
+    const bool b = t.block == 64 || t.block == 128 || t.block == 256;
+    const bool j = t.per_thread == 1 || t.per_thread == 2 || t.per_thread == 4 ||
+                   t.per_thread == 8;
+    const bool u = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
+    return b && j && u && (t.nt_store == 0 || t.nt_store == 1) && t.wg_per_cu >= 0 &&
+           t.wg_per_cu <= 64;
+}
+
+// The aligned vector kernel applies when every row's flat volume and stack
+// offsets keep one residue mod 4 across planes and the buffers are aligned.
+inline bool vec_ok(const dsk_tune &t, dsk_dims d, int64_t width, const void *in, int in_is_f32,
+                   const float *vol) {
+    if (t.per_thread < 4) return false;
+    if ((int64_t)d.planes * d.rows * d.cols < 64) return false;
+    if (width >= (int64_t(1) << 27) || d.cols >= (1 << 27)) return false;
+    if (((int64_t)d.rows * width) % 4 != 0 || ((int64_t)d.rows * d.cols) % 4 != 0) return false;
+    const uintptr_t ia = in_is_f32 ? 15 : 7;
+    if ((uintptr_t)in & ia) return false;
+    if (vol && ((uintptr_t)vol & 15)) return false;
+    return true;
+}
+
+// Column tiles of one output row.  The vector kernel's first tile starts up
+// to 3 columns left of 0, so it may need one more tile.
+inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec) {
+    const int64_t tile = (int64_t)t.block * t.per_thread;
+    return (width + (vec ? 3 : 0) + tile - 1) / tile;
+}
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// Calls f(IC<block>, IC<per_thread>, IC<unroll>, bool_constant<nt>) for a
+// validated launch shape.
+template <typename F>
+auto dispatch_tune(const dsk_tune &t, F &&f) {
+    auto with_u = [&](auto B, auto P) {
+        auto with_nt = [&](auto U) {
+            return t.nt_store ? f(B, P, U, std::true_type{}) : f(B, P, U, std::false_type{});
+        };
+        switch (t.unroll) {
+        case 1: return with_nt(IC<1>{});
+        case 2: return with_nt(IC<2>{});
+        default: return with_nt(IC<4>{});
+        }
+    };
+    auto with_p = [&](auto B) {
+        switch (t.per_thread) {
+        case 1: return with_u(B, IC<1>{});
+        case 2: return with_u(B, IC<2>{});
+        case 4: return with_u(B, IC<4>{});
+        default: return with_u(B, IC<8>{});
+        }
+    };
+    switch (t.block) {
+    case 64: return with_p(IC<64>{});
+    case 128: return with_p(IC<128>{});
+    default: return with_p(IC<256>{});
+    }
+}
+
+// Output width and columns stay below 2^30 so that every column index of the
+// kernels (x' and x' - k, with k clamped to +-2^30) fits the index types.
+inline int check_frame(dsk_dims d, int64_t origin, int64_t width) {
+    if (width <= 0 || width >= (int64_t(1) << 30) || d.cols >= (1 << 30)) return DSK_ESHAPE;
+    if (origin < -(int64_t(1) << 52) || origin > (int64_t(1) << 52)) return DSK_ESHAPE;
+    return DSK_OK;
+}
+
+inline int hip_status(hipError_t e) { return e == hipSuccess ? DSK_OK : DSK_EHIP; }
+
+// Launchers (deskew.hip) used by the batch translation unit.
+int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs,
+                   double shift, int64_t origin, float *vol, float *psum, float *pmax,
+                   int64_t width, const dsk_tune &t, hipStream_t stream);
+
+}  // namespace dsk

@@ -1,0 +1,234 @@
+// deskew.hip -- C ABI of the single-stack path: geometry plan (Eq. 1 and the
+// remap frame), forward deskew with fused projections, adjoint and shear
+// gradient.  Host code validates everything before enqueueing a kernel.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common.hpp"
+#include "deskew.h"
+#include "kernels.hpp"
+
+using namespace dsk;
+
+extern "C" const char *dsk_status_string(int status) {
+    switch (status) {
+    case DSK_OK: return "ok";
+    case DSK_EINVAL: return "invalid argument";
+    case DSK_ESHAPE: return "size out of range";
+    case DSK_EHIP: return "HIP runtime error";
+    case DSK_ENOMEM: return "out of memory";
+    case DSK_EBUDGET: return "over the memory budget";
+    default: return "unknown status";
+    }
+}
+
+// Eq. 1: l = z cos(alpha); in pixels of sample-space size p.
+extern "C" int dsk_shift_px(dsk_geom g, double *shift_px) {
+    if (!shift_px) return DSK_EINVAL;
+    if (!std::isfinite(g.angle_deg) || !std::isfinite(g.step_um) ||
+        !std::isfinite(g.pixel_um) || !(g.pixel_um > 0.0))
+        return DSK_EINVAL;
+    const double pi = 3.14159265358979323846;
+    const double alpha = g.angle_deg * pi / 180.0;
+    *shift_px = (g.step_um * std::cos(alpha)) / g.pixel_um;
+    return DSK_OK;
+}
+
+// The larger image of the remap: origin b = floor(min o), width
+// W = C + ceil(max o) - b, with o[n] = n * s unless offsets are given.
+extern "C" int dsk_plan(dsk_dims d, const double *offsets_px, double shift_px,
+                        int64_t *out_width, int64_t *origin) {
+    if (!out_width || !origin || !dims_ok(d)) return DSK_EINVAL;
+    if (!offsets_px && !std::isfinite(shift_px)) return DSK_EINVAL;
+    double lo = 0.0, hi = 0.0;
+    for (int32_t n = 0; n < d.planes; ++n) {
+        const double o = offsets_px ? offsets_px[n] : (double)n * shift_px;
+        if (!std::isfinite(o)) return DSK_EINVAL;
+        if (n == 0 || o < lo) lo = o;
+        if (n == 0 || o > hi) hi = o;
+    }
+    const double fb = std::floor(lo), fh = std::ceil(hi);
+    if (std::fabs(fb) > 4.0e15 || std::fabs(fh) > 4.0e15) return DSK_ESHAPE;
+    const int64_t b = (int64_t)fb;
+    const int64_t w = (int64_t)d.cols + (int64_t)fh - b;
+    if (w <= 0 || w >= (int64_t(1) << 30)) return DSK_ESHAPE;
+    *origin = b;
+    *out_width = w;
+    return DSK_OK;
+}
+
+namespace dsk {
+
+template <typename TIn, int B, int PT, int U, bool NT>
+static hipError_t fwd_launch(const FwdArgs<TIn> &a, bool vec, int64_t tiles, hipStream_t s) {
+    const dim3 grid((unsigned)(tiles * a.R)), block(B);
+    if constexpr (PT >= 4) {
+        if (vec) {
+            hipLaunchKernelGGL((k_forward_vec<TIn, B, PT / 4, U, NT>), grid, block, 0, s, a,
+                               (int)tiles);
+            return hipGetLastError();
+        }
+    }
+    hipLaunchKernelGGL((k_forward_scalar<TIn, B, PT, NT>), grid, block, 0, s, a, (int)tiles);
+    return hipGetLastError();
+}
+
+template <typename TIn>
+static hipError_t fwd_dispatch(const FwdArgs<TIn> &a, const dsk_tune &t, bool vec, int64_t tiles,
+                               hipStream_t s) {
+    return dispatch_tune(t, [&](auto B, auto P, auto U, auto NT) {
+        return fwd_launch<TIn, decltype(B)::value, decltype(P)::value, decltype(U)::value,
+                          decltype(NT)::value>(a, vec, tiles, s);
+    });
+}
+
+int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs, double shift,
+                   int64_t origin, float *vol, float *psum, float *pmax, int64_t width,
+                   const dsk_tune &t, hipStream_t stream) {
+    if (!in || !dims_ok(d) || (!vol && !psum && !pmax)) return DSK_EINVAL;
+    if (!offs && !std::isfinite(shift)) return DSK_EINVAL;
+    if (!tune_ok(t)) return DSK_EINVAL;
+    int st = check_frame(d, origin, width);
+    if (st != DSK_OK) return st;
+    const bool vec = vec_ok(t, d, width, in, in_is_f32, vol);
+    const int64_t tiles = tiles_x(width, t, vec);
+    if (tiles * (int64_t)d.rows > kMaxI32) return DSK_ESHAPE;
+    hipError_t e;
+    if (in_is_f32) {
+        FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
+                         width, d.planes, d.rows, d.cols};
+        e = fwd_dispatch<float>(a, t, vec, tiles, stream);
+    } else {
+        FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
+                            width, d.planes, d.rows, d.cols};
+        e = fwd_dispatch<uint16_t>(a, t, vec, tiles, stream);
+    }
+    return hip_status(e);
+}
+
+}  // namespace dsk
+
+extern "C" int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float *vol,
+                              float *psum, float *pmax, int64_t out_width,
+                              hipStream_t stream) {
+    if (!dims_ok(d) || out_width < 0) return DSK_EINVAL;
+    double s = 0.0;
+    int st = dsk_shift_px(g, &s);
+    if (st != DSK_OK) return st;
+    int64_t w = 0, b = 0;
+    st = dsk_plan(d, nullptr, s, &w, &b);
+    if (st != DSK_OK) return st;
+    if (out_width > 0) w = out_width;
+    return launch_forward(in, 0, d, nullptr, s, b, vol, psum, pmax, w, kDefaultTune, stream);
+}
+
+extern "C" int dsk_deskew_offsets_u16(const uint16_t *in, dsk_dims d, const double *offsets_dev,
+                                      int64_t origin, float *vol, float *psum, float *pmax,
+                                      int64_t out_width, hipStream_t stream) {
+    if (!offsets_dev || out_width <= 0) return DSK_EINVAL;
+    return launch_forward(in, 0, d, offsets_dev, 0.0, origin, vol, psum, pmax, out_width,
+                          kDefaultTune, stream);
+}
+
+extern "C" int dsk_deskew_offsets_f32(const float *in, dsk_dims d, const double *offsets_dev,
+                                      int64_t origin, float *vol, float *psum, float *pmax,
+                                      int64_t out_width, hipStream_t stream) {
+    if (!offsets_dev || out_width <= 0) return DSK_EINVAL;
+    return launch_forward(in, 1, d, offsets_dev, 0.0, origin, vol, psum, pmax, out_width,
+                          kDefaultTune, stream);
+}
+
+extern "C" int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
+                                        const double *offsets_dev, double shift_px,
+                                        int64_t origin, float *vol, float *psum, float *pmax,
+                                        int64_t out_width, const dsk_tune *tune,
+                                        hipStream_t stream) {
+    if (out_width <= 0) return DSK_EINVAL;
+    const dsk_tune t = tune ? *tune : kDefaultTune;
+    return launch_forward(in, in_is_f32 ? 1 : 0, d, offsets_dev, shift_px, origin, vol, psum,
+                          pmax, out_width, t, stream);
+}
+
+// ---------------------------------------------------------------- backward
+
+namespace {
+
+constexpr int kBwdBlock = 256;
+
+// Rows per backward workgroup: about 8192 raw columns per workgroup.
+int bwd_rows_per_block(dsk_dims d) {
+    int64_t rpb = 8192 / (int64_t)d.cols;
+    if (rpb < 1) rpb = 1;
+    if (rpb > d.rows) rpb = d.rows;
+    return (int)rpb;
+}
+
+int bwd_groups(dsk_dims d) {
+    const int rpb = bwd_rows_per_block(d);
+    return (d.rows + rpb - 1) / rpb;
+}
+
+int launch_backward(const float *in, const float *gvol, dsk_dims d, const double *offs,
+                    int64_t origin, int64_t width, float *gin, double *goff, void *ws,
+                    size_t ws_bytes, hipStream_t stream) {
+    if (!gvol || !offs || !dims_ok(d) || (!gin && !goff)) return DSK_EINVAL;
+    if (goff && (!in || !ws)) return DSK_EINVAL;
+    int st = check_frame(d, origin, width);
+    if (st != DSK_OK) return st;
+    const int G = bwd_groups(d);
+    const int64_t blocks = (int64_t)G * d.planes;
+    if (blocks > kMaxI32) return DSK_ESHAPE;
+    if (goff && ws_bytes < dsk_shear_grad_workspace_bytes(d)) return DSK_ESHAPE;
+    BwdArgs a{in, gvol, gin, (double *)ws, offs, 0.0, (double)origin, width,
+              d.planes, d.rows, d.cols, bwd_rows_per_block(d), G};
+    const dim3 grid((unsigned)blocks), block(kBwdBlock);
+    if (gin && goff)
+        hipLaunchKernelGGL((k_backward<kBwdBlock, true, true>), grid, block, 0, stream, a);
+    else if (gin)
+        hipLaunchKernelGGL((k_backward<kBwdBlock, true, false>), grid, block, 0, stream, a);
+    else
+        hipLaunchKernelGGL((k_backward<kBwdBlock, false, true>), grid, block, 0, stream, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return DSK_EHIP;
+    if (goff) {
+        const int fb = 64;
+        hipLaunchKernelGGL(k_backward_finalize<0>, dim3((d.planes + fb - 1) / fb), dim3(fb), 0,
+                           stream, (const double *)ws, d.planes, G, goff);
+        e = hipGetLastError();
+    }
+    return hip_status(e);
+}
+
+}  // namespace
+
+extern "C" size_t dsk_shear_grad_workspace_bytes(dsk_dims d) {
+    if (!dims_ok(d)) return 0;
+    return (size_t)bwd_groups(d) * (size_t)d.planes * sizeof(double);
+}
+
+extern "C" int dsk_deskew_adjoint_f32(const float *grad_vol, dsk_dims d,
+                                      const double *offsets_dev, int64_t origin,
+                                      int64_t out_width, float *grad_in, hipStream_t stream) {
+    if (!grad_in) return DSK_EINVAL;
+    return launch_backward(nullptr, grad_vol, d, offsets_dev, origin, out_width, grad_in,
+                           nullptr, nullptr, 0, stream);
+}
+
+extern "C" int dsk_shear_grad_f32(const float *in, const float *grad_vol, dsk_dims d,
+                                  const double *offsets_dev, int64_t origin, int64_t out_width,
+                                  double *grad_offsets, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream) {
+    if (!grad_offsets) return DSK_EINVAL;
+    return launch_backward(in, grad_vol, d, offsets_dev, origin, out_width, nullptr,
+                           grad_offsets, workspace, workspace_bytes, stream);
+}
+
+extern "C" int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims d,
+                                const double *offsets_dev, int64_t origin, int64_t out_width,
+                                float *grad_in, double *grad_offsets, void *workspace,
+                                size_t workspace_bytes, hipStream_t stream) {
+    return launch_backward(in, grad_vol, d, offsets_dev, origin, out_width, grad_in,
+                           grad_offsets, workspace, workspace_bytes, stream);
+}

@@ -1,0 +1,109 @@
+"""Host-side checks of libdeskew.so: it loads without a GPU, exports every
+symbol include/deskew.h declares, and its host-only planning calls follow
+Eq. 1 and the remap frame.  No kernel is launched here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2211_00645_amd import _lib as L
+from paper_2211_00645_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"\b(dsk_\w+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in sorted(names):
+        assert hasattr(lib, n), f"{n} declared in include/ but not exported"
+    assert names <= set(L._SIGS), "binding lacks a declared entry point"
+
+
+def test_status_strings():
+    assert L.status_string(0) == "ok"
+    assert "invalid" in L.status_string(-1)
+    assert L.status_string(12345) == "unknown status"
+
+
+def test_shift_px_eq1():
+    assert api.shift_px(30.0, 0.4, 0.115) == pytest.approx(0.4 * math.sqrt(3) / 2 / 0.115,
+                                                           rel=1e-15)
+    assert api.shift_px(60.0, 1.0, 1.0) == pytest.approx(0.5, abs=1e-15)
+    assert api.shift_px(0.0, -0.4, 0.2) == pytest.approx(-2.0, rel=1e-15)
+    out = ctypes.c_double()
+    lib = L.lib()
+    assert lib.dsk_shift_px(L.Geom(30.0, 0.4, 0.0), ctypes.byref(out)) == L.DSK_EINVAL
+    assert lib.dsk_shift_px(L.Geom(float("nan"), 0.4, 0.1), ctypes.byref(out)) == L.DSK_EINVAL
+    assert lib.dsk_shift_px(L.Geom(30.0, float("inf"), 0.1), ctypes.byref(out)) == L.DSK_EINVAL
+    assert lib.dsk_shift_px(L.Geom(30.0, 0.4, 0.1), None) == L.DSK_EINVAL
+
+
+@pytest.mark.parametrize("n,c,s,expect", [
+    (64, 256, 0.4 * math.sqrt(3) / 2 / 0.115, (446, 0)),       # 30 deg, 0.4 um, 115 nm
+    (512, 2048, 0.4 * math.cos(math.radians(35)) / 0.115, (3504, 0)),
+    (64, 256, 3.0, (445, 0)),                                   # integer shift
+    (4, 10, -0.75, (13, -3)),                                   # reversed scan
+    (1, 7, 5.0, (7, 0)),                                        # one plane
+    (50, 87, (3652 - 87) / 49, (3652, 0)),                      # paper display size
+])
+def test_plan_frame(n, c, s, expect):
+    assert api.plan((n, 3, c), shift=s) == expect
+
+
+def test_plan_with_offsets_and_errors():
+    assert api.plan((3, 1, 10), offsets=np.array([0.5, -1.25, 2.0])) == (14, -2)
+    with pytest.raises(L.DeskewError):
+        api.plan((3, 1, 10), offsets=np.array([0.0, float("nan"), 1.0]))
+    with pytest.raises(L.DeskewError):
+        api.plan((0, 1, 10), shift=1.0)
+    with pytest.raises(L.DeskewError):
+        api.plan((3, 1, 10), shift=1e12)        # W beyond int32
+
+
+def test_workspace_and_table_sizes():
+    lib = L.lib()
+    assert lib.dsk_shear_grad_workspace_bytes(L.Dims(256, 512, 1024)) >= 256 * 8
+    assert lib.dsk_shear_grad_workspace_bytes(L.Dims(0, 1, 1)) == 0
+    assert lib.dsk_jobs_table_bytes(64) >= 64 * 64
+    assert lib.dsk_jobs_table_bytes(0) == 0
+
+
+def test_launch_entry_points_reject_bad_arguments_before_any_launch():
+    """Validation runs on the host; these calls never reach a kernel."""
+    lib = L.lib()
+    d = L.Dims(4, 2, 8)
+    g = L.Geom(30.0, 0.4, 0.115)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.dsk_deskew_u16(None, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_u16(fake, d, g, None, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_u16(fake, L.Dims(0, 2, 8), g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_u16(fake, d, L.Geom(30.0, 0.4, -1.0), fake, None, None, 0,
+                              None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_offsets_u16(fake, d, None, 0, fake, None, None, 10,
+                                      None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_offsets_f32(fake, d, fake, 0, fake, None, None, 0,
+                                      None) == L.DSK_EINVAL
+    bad = L.Tune(96, 4, 0, 0)
+    assert lib.dsk_deskew_offsets_tuned(fake, 0, d, None, 1.0, 0, fake, None, None, 16,
+                                        ctypes.byref(bad), None) == L.DSK_EINVAL
+    assert lib.dsk_backward_f32(fake, fake, d, fake, 0, 16, None, None, None, 0,
+                                None) == L.DSK_EINVAL
+    assert lib.dsk_shear_grad_f32(fake, fake, d, fake, 0, 16, fake, fake, 0,
+                                  None) == L.DSK_ESHAPE
+    assert lib.dsk_jobs_launch(None, 1, fake, fake, 1024, None, None) == L.DSK_EINVAL
+    assert lib.dsk_batch_launch(None, None) == L.DSK_EINVAL
+    assert lib.dsk_batch_destroy(None) == L.DSK_EINVAL

@@ -1,0 +1,258 @@
+"""Parity of the HIP forward deskew + projections with the CPU oracle.
+
+Bar: bit-exact where every plane sits at an integer offset; otherwise, per
+voxel, |gpu - oracle| <= 1e-5 * (whi*|a| + wlo*|b|) (for uint16 input this
+is <= 1e-5 * |oracle|), padding voxels exactly zero, and the FP64-summed
+projection within 1e-5 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2211_00645_amd as dsk
+from paper_2211_00645_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-5
+DEV = "cuda:0"
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def _interp_scale(stack, offsets, origin, width, rows=None):
+    """Per-voxel magnitude whi*|a| + wlo*|b| (the oracle on |stack|)."""
+    return oracle.deskew(np.abs(stack) if stack.dtype != np.uint16 else stack, offsets,
+                         origin=origin, width=width, rows=rows)["vol"].astype(np.float64)
+
+
+def _check_close(gpu, ref, scale, what):
+    g = gpu.astype(np.float64)
+    r = ref.astype(np.float64)
+    err = np.abs(g - r)
+    bound = RTOL * scale + 1e-30
+    bad = err > bound
+    assert not bad.any(), (f"{what}: {bad.sum()} voxels over tolerance, worst "
+                           f"{(err / np.maximum(scale, 1e-30)).max():.3e}")
+
+
+def _check_zero_padding(gpu_vol, ref_vol, what):
+    z = ref_vol == 0
+    assert (gpu_vol[z] == 0).all(), f"{what}: nonzero where the oracle has padding"
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    s = synth.blob_stack((64, 128, 256), 50, 0)
+    return s, s.numpy()
+
+
+def test_config1_integer_shift_bit_exact(cfg1):
+    st, sn = cfg1
+    _say("forward: config 1, integer shift 3 px/plane")
+    off = np.arange(64, dtype=np.float64) * 3.0
+    ref = oracle.deskew(sn, off)
+    out = dsk.deskew(st.to(DEV), offsets=off)
+    torch.cuda.synchronize()
+    assert (out["origin"], out["width"]) == (ref["origin"], ref["width"]) == (0, 445)
+    assert _to_np(out["vol"]).tobytes() == ref["vol"].tobytes()
+    assert _to_np(out["psum"]).tobytes() == ref["psum"].tobytes()
+    assert _to_np(out["pmax"]).tobytes() == ref["pmax"].tobytes()
+
+
+def test_config1_fractional(cfg1):
+    st, sn = cfg1
+    _say("forward: config 1, 30 deg, 0.4 um, 0.115 um")
+    s = oracle.shift_px(30.0, 0.4, 0.115)
+    off = oracle.offsets_uniform(64, s)
+    ref = oracle.deskew(sn, off)
+    out = dsk.deskew(st.to(DEV), 30.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    assert (out["origin"], out["width"]) == (ref["origin"], ref["width"]) == (0, 446)
+    v = _to_np(out["vol"])
+    _check_close(v, ref["vol"], np.abs(ref["vol"]).astype(np.float64), "vol")
+    _check_zero_padding(v, ref["vol"], "vol")
+    _check_close(_to_np(out["psum"]), ref["psum"], np.abs(ref["psum"]).astype(np.float64),
+                 "psum")
+    _check_close(_to_np(out["pmax"]), ref["pmax"], np.abs(ref["pmax"]).astype(np.float64),
+                 "pmax")
+
+
+TUNES = [dict(block=b, per_thread=j, nt_store=nt, unroll=u)
+         for b in (64, 128, 256) for j in (1, 2, 4, 8) for nt in (0, 1) for u in (1, 2, 4)
+         if not (j < 4 and u > 1)]
+
+
+def test_every_launch_shape_is_bitwise_identical(cfg1):
+    st, _ = cfg1
+    _say("forward: launch shapes")
+    x = st.to(DEV)
+    off = oracle.offsets_uniform(64, oracle.shift_px(30.0, 0.4, 0.115))
+    base = dsk.deskew(x, offsets=off)
+    for t in TUNES:
+        o = dsk.deskew(x, offsets=off, tune=t)
+        for k in ("vol", "psum", "pmax"):
+            assert torch.equal(o[k], base[k]), (t, k)
+    # the uniform-scan path (offsets computed on the device) matches too
+    o = dsk.deskew(x, 30.0, 0.4, 0.115)
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(o[k], base[k]), k
+
+
+def test_misaligned_buffers_match_aligned(cfg1):
+    """Stacks and volumes that are not 16-byte aligned take the scalar kernel;
+    results are bitwise those of the aligned vector kernel."""
+    st, _ = cfg1
+    x = st.to(DEV)
+    off = oracle.offsets_uniform(64, oracle.shift_px(30.0, 0.4, 0.115))
+    base = dsk.deskew(x, offsets=off)
+    flat = torch.empty(x.numel() + 1, dtype=torch.uint16, device=DEV)
+    xm = flat[1:].view(x.shape)
+    xm.copy_(x)
+    assert xm.data_ptr() % 16 != 0
+    w = base["width"]
+    vflat = torch.empty(64 * 128 * w + 1, dtype=torch.float32, device=DEV)
+    vm = vflat[1:].view(64, 128, w)
+    o = dsk.deskew(xm, offsets=off, out={"vol": vm})
+    for k in ("psum", "pmax"):
+        assert torch.equal(o[k], base[k]), k
+    assert torch.equal(vm, base["vol"])
+
+
+def test_determinism(cfg1):
+    st, _ = cfg1
+    x = st.to(DEV)
+    a = dsk.deskew(x, 35.0, 0.4, 0.115)
+    b = dsk.deskew(x, 35.0, 0.4, 0.115)
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(a[k], b[k])
+
+
+RAGGED = [
+    # (planes, rows, cols, offsets kind, seed)
+    (1, 1, 1, "frac", 1),
+    (1, 3, 17, "frac", 2),
+    (7, 5, 33, "neg", 3),
+    (13, 9, 257, "frac", 4),
+    (33, 7, 513, "jitter", 5),
+    (5, 3, 1000, "int", 6),
+    (64, 4, 64, "big", 7),         # W = 64 + 63*40 = 2584: many tiles, mostly padding
+    (3, 2, 5, "zero", 8),
+    (4, 4, 7, "frac", 9),          # rows*cols % 4 == 0, W odd
+    (9, 12, 300, "neg", 10),       # vector kernel with negative offsets
+    (2, 2, 2, "frac", 11),         # tiny stack: scalar kernel
+]
+
+
+def _offsets(kind, n, seed):
+    rng = np.random.default_rng(seed)
+    if kind == "frac":
+        return oracle.offsets_uniform(n, 2.718281828)
+    if kind == "neg":
+        return oracle.offsets_uniform(n, -1.4142135)
+    if kind == "jitter":
+        return np.cumsum(np.r_[0.0, rng.uniform(0.5, 3.5, n - 1)])
+    if kind == "int":
+        return np.arange(n, dtype=np.float64) * -7.0
+    if kind == "big":
+        return oracle.offsets_uniform(n, 40.0)
+    if kind == "zero":
+        return np.zeros(n)
+    raise ValueError(kind)
+
+
+@pytest.mark.parametrize("n,r,c,kind,seed", RAGGED)
+@pytest.mark.parametrize("dtype", ["u16", "f32"])
+def test_ragged_shapes(n, r, c, kind, seed, dtype):
+    _say(f"forward: ragged {n}x{r}x{c} {kind} {dtype}")
+    if dtype == "u16":
+        st = synth.blob_stack((n, r, c), max(1, n * r * c // 20000), seed)
+    else:
+        st = synth.blob_stack((n, r, c), max(1, n * r * c // 20000), seed, dtype="f32")
+        st = st - 0.25 * st.mean()          # signed values
+    sn = st.numpy()
+    off = _offsets(kind, n, seed)
+    ref = oracle.deskew(sn, off)
+    out = dsk.deskew(st.to(DEV), offsets=off)
+    torch.cuda.synchronize()
+    assert (out["origin"], out["width"]) == (ref["origin"], ref["width"])
+    v = _to_np(out["vol"])
+    if kind in ("int", "zero"):
+        assert v.tobytes() == ref["vol"].tobytes()
+        assert _to_np(out["psum"]).tobytes() == ref["psum"].tobytes()
+        assert _to_np(out["pmax"]).tobytes() == ref["pmax"].tobytes()
+        return
+    scale = _interp_scale(sn, off, ref["origin"], ref["width"])
+    _check_close(v, ref["vol"], scale, "vol")
+    _check_zero_padding(v, ref["vol"], "vol")
+    pscale = scale.sum(0)
+    _check_close(_to_np(out["psum"]), ref["psum"], pscale, "psum")
+    _check_close(_to_np(out["pmax"]), ref["pmax"], scale.max(0), "pmax")
+
+
+def test_clipped_and_padded_width_and_projection_only(cfg1):
+    st, sn = cfg1
+    x = st.to(DEV)
+    off = oracle.offsets_uniform(64, oracle.shift_px(30.0, 0.4, 0.115))
+    for w in (300, 446, 500):
+        ref = oracle.deskew(sn, off, origin=0, width=w)
+        out = dsk.deskew(x, offsets=off, origin=0, width=w)
+        torch.cuda.synchronize()
+        _check_close(_to_np(out["vol"]), ref["vol"], np.abs(ref["vol"]).astype(np.float64),
+                     f"vol w={w}")
+        _check_zero_padding(_to_np(out["vol"]), ref["vol"], f"vol w={w}")
+    full = dsk.deskew(x, offsets=off)
+    proj = dsk.deskew(x, offsets=off, vol=False)
+    assert "vol" not in proj
+    assert torch.equal(proj["psum"], full["psum"]) and torch.equal(proj["pmax"], full["pmax"])
+    vol_only = dsk.deskew(x, offsets=off, psum=False, pmax=False)
+    assert torch.equal(vol_only["vol"], full["vol"])
+
+
+def test_live_scale_config2_sampled_rows():
+    """512 x 512 x 2048 uint16 at 35 deg: every output of sampled rows, in the
+    launch configuration the benchmark times."""
+    _say("forward: config 2 (512x512x2048), generating")
+    st = synth.blob_stack((512, 512, 2048), 2000, 2, device=DEV)
+    torch.cuda.synchronize()
+    _say("forward: config 2 deskew")
+    out = dsk.deskew(st, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    assert out["width"] == 3504 and out["origin"] == 0
+    rows = [0, 1, 137, 255, 256, 400, 511]
+    sn = st.cpu().numpy()
+    off = oracle.offsets_uniform(512, oracle.shift_px(35.0, 0.4, 0.115))
+    vol = out["vol"]
+    for r in rows:
+        _say(f"forward: config 2 row {r}")
+        ref = oracle.deskew(sn, off, rows=(r, r + 1))
+        g = _to_np(vol[:, r:r + 1, :])
+        _check_close(g, ref["vol"], np.abs(ref["vol"]).astype(np.float64), f"vol row {r}")
+        _check_zero_padding(g, ref["vol"], f"vol row {r}")
+        _check_close(_to_np(out["psum"][r:r + 1]), ref["psum"],
+                     np.abs(ref["psum"]).astype(np.float64), f"psum row {r}")
+        _check_close(_to_np(out["pmax"][r:r + 1]), ref["pmax"],
+                     np.abs(ref["pmax"]).astype(np.float64), f"pmax row {r}")
+    # integral property over the whole stack: sum of Psum == sum of the stack
+    tot_in = float(st.to(torch.int64).sum())
+    tot_out = float(out["psum"].double().sum())
+    assert tot_out == pytest.approx(tot_in, rel=1e-6)
+
+
+def test_invalid_arguments_raise():
+    x = torch.zeros((4, 2, 8), dtype=torch.uint16, device=DEV)
+    with pytest.raises(ValueError):
+        dsk.deskew(x.cpu(), 30.0, 0.4, 0.115)
+    with pytest.raises(Exception):
+        dsk.deskew(x, 30.0, 0.4, -1.0)
+    with pytest.raises(ValueError):
+        dsk.deskew(x.transpose(1, 2), 30.0, 0.4, 0.115)
