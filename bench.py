@@ -102,6 +102,109 @@ def copy_ceiling(torch, nbytes=4 << 30, reps=5):
     return 2 * nbytes / (statistics.median(ts) * 1e-3) / 1e9
 
 
+def _median_ms(torch, fn, reps):
+    ts = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return statistics.median(ts)
+
+
+def bench_batch(torch, dsk, synth):
+    """64 ragged uint16 stacks: one persistent launch (graph replay) against
+    64 plain launches on one stream; outputs compared bitwise."""
+    from paper_2211_00645_amd.batch import Batch
+    jobs = synth.ragged_jobs(64, seed=0)
+    stacks, geoms = [], []
+    for i, j in enumerate(jobs):
+        shp = (j["planes"], j["rows"], j["cols"])
+        stacks.append(synth.blob_stack(shp, synth.blobs_for_volume(*shp), 1000 + i, device="cuda"))
+        geoms.append((j["angle_deg"], j["step_um"], j["pixel_um"]))
+    torch.cuda.synchronize()
+    b = Batch(stacks, geoms, cache_path=os.path.join(ROOT, "gpurun_out", "tune_cache.json")
+              if os.path.isdir(os.path.join(ROOT, "gpurun_out")) else None)
+    tune = b.tune
+    alg = sum(2 * o["vol"].numel() // o["width"] * s.shape[2] + 4 * o["vol"].numel()
+              + 8 * o["psum"].numel() for o, s in zip(b.outputs, stacks))
+    vox = sum(o["vol"].numel() for o in b.outputs)
+    b.launch()
+    ms_graph = _median_ms(torch, b.launch, 5)
+    outs = b.outputs
+
+    def plain():
+        for s, g, o in zip(stacks, geoms, outs):
+            dsk.deskew(s, *g, out=o_plain[id(o)])
+    o_plain = {id(o): {k: torch.empty_like(o[k]) for k in ("vol", "psum", "pmax")}
+               for o in outs}
+    plain()
+    ms_plain = _median_ms(torch, plain, 5)
+    torch.cuda.synchronize()
+    same = all(torch.equal(o[k], o_plain[id(o)][k]) for o in outs for k in ("vol", "psum", "pmax"))
+    b.close()
+    del b, outs, o_plain, stacks
+    torch.cuda.empty_cache()
+    return {"workload": "64 ragged uint16 stacks (planes 50-400, rows 256/512/1024, "
+                        "cols 512-2048, 30/35/45 deg), seed 0",
+            "graph_ms": ms_graph, "plain_64_launches_ms": ms_plain,
+            "speedup": ms_plain / ms_graph, "gbs_graph": alg / ms_graph / 1e6,
+            "voxels_per_s_graph": vox / ms_graph * 1e3, "algorithmic_bytes": alg,
+            "bitwise_equal": same, "tune": tune}
+
+
+def bench_autograd(torch, dsk, synth):
+    """Forward (float32) + fused backward on 256 x 512 x 1024, frame 1793."""
+    n, r, c, w = 256, 512, 1024, 1793
+    st = synth.blob_stack((n, r, c), 2000, 4, device="cuda", dtype="f32")
+    offs = torch.arange(n, dtype=torch.float64, device="cuda") * dsk.shift_px(30.0, STEP, PIXEL)
+    out = {"vol": torch.empty((n, r, w), device="cuda")}
+    gd = torch.empty((n, r, w), device="cuda").uniform_()
+    fwd = _median_ms(torch, lambda: dsk.deskew(st, offsets=offs, origin=0, width=w, out=out,
+                                                psum=False, pmax=False), 10)
+    bwd = _median_ms(torch, lambda: dsk.backward(st, gd, offs, 0), 10)
+    del st, out, gd
+    torch.cuda.empty_cache()
+    fb = 4 * n * r * c + 4 * n * r * w
+    bb = 4 * n * r * w + 4 * n * r * c + 4 * n * r * c
+    return {"workload": "float32 256x512x1024, frame 1793",
+            "forward_ms": fwd, "forward_gbs": fb / fwd / 1e6,
+            "backward_ms": bwd, "backward_gbs": bb / bwd / 1e6}
+
+
+def bench_serving(torch, dsk, synth, n_req, rate):
+    """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
+    200 GB budget; continuous batching vs one stack at a time."""
+    from paper_2211_00645_amd import serving as sv
+    pool = {}
+    for k, (r, c) in enumerate([(512, 1024), (512, 2048), (1024, 1024), (1024, 2048)]):
+        for ch in range(2):
+            pool[(r, c, ch)] = synth.blob_stack((400, r, c), synth.blobs_for_volume(400, r, c),
+                                                500 + 2 * k + ch, device="cuda")
+    torch.cuda.synchronize()
+    res = {"workload": f"{n_req} 2-channel stacks, Poisson {rate} Hz, 200 GB budget"}
+    # warm the allocator and the kernels
+    ex = sv.GPUExecutor(pool, n_slots=4)
+    sv.Scheduler(ex, 200 << 30, n_slots=4).run(sv.make_requests(synth.serving_trace(8, 1e6, 9)))
+    for mode in ("live", "burst"):
+        r_ = rate if mode == "live" else 1e9
+        tr = synth.serving_trace(n_req, r_, 7)
+        ex = sv.GPUExecutor(pool, n_slots=4)
+        sch = sv.Scheduler(ex, 200 << 30, n_slots=4, max_batch=8)
+        res[mode] = dict(sv.summarize(sch.run(sv.make_requests(tr))), launches=sch.launches,
+                         peak_gb=sch.peak_used / 1e9)
+        res[mode + "_plain"] = sv.summarize(sv.run_plain(sv.GPUExecutor(pool, n_slots=1),
+                                                         sv.make_requests(tr)))
+        log(f"serving {mode}: p50 {res[mode]['latency_p50_ms']:.2f} ms p99 "
+            f"{res[mode]['latency_p99_ms']:.2f} ms; plain p99 "
+            f"{res[mode + '_plain']['latency_p99_ms']:.2f} ms")
+    del pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +212,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--extras", default="batch,autograd,serving",
+                    help="comma list of extra measurements (batch, autograd, serving) or none")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -170,12 +277,29 @@ def main():
     log(f"device copy ceiling {copy_gbs:.0f} GB/s")
 
     cpu = None
+    del outs
+    torch.cuda.synchronize()
     if args.cpu_seconds > 0:
-        del outs
-        torch.cuda.synchronize()
         host = stack.cpu().numpy()
         cpu = cpu_baseline(host, args.cpu_seconds)
         cpu.pop("seconds", None)
+        del host
+    del stack
+    torch.cuda.empty_cache()
+
+    extras = [e for e in args.extras.split(",") if e and e != "none"]
+    ext = {}
+    if "batch" in extras:
+        log("batch: 64 ragged stacks")
+        ext["batch"] = bench_batch(torch, dsk, synth)
+        log(f"batch: graph {ext['batch']['graph_ms']:.2f} ms vs plain "
+            f"{ext['batch']['plain_64_launches_ms']:.2f} ms")
+    if "autograd" in extras:
+        log("autograd: forward + backward")
+        ext["autograd"] = bench_autograd(torch, dsk, synth)
+    if "serving" in extras:
+        log("serving")
+        ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)
 
     rec = {
         "metric": METRIC,
@@ -205,6 +329,9 @@ def main():
         "copy_ceiling_gbs": copy_gbs,
         "cpu_baseline": cpu,
     }
+    if "serving" in ext:
+        rec["latency_p99_ms_live"] = ext["serving"]["live"]["latency_p99_ms"]
+    rec.update(ext)
     print(json.dumps(rec), flush=True)
 
 

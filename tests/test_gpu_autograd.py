@@ -1,0 +1,193 @@
+"""Adjoint and shear-gradient kernels: parity with the CPU oracle, the
+dot-product adjoint test, finite differences, and angle calibration.
+
+Float32 stacks, 256 x 512 x 1024 at the full size (frame fixed at W = 1793,
+the width at 30 degrees, 0.4 um step, 0.115 um pixels).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2211_00645_amd as dsk
+from paper_2211_00645_amd import autograd as ag
+from paper_2211_00645_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+N4, R4, C4, W4 = 256, 512, 1024, 1793
+STEP, PIXEL = 0.4, 0.115
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _dev(a, dtype=None):
+    t = torch.as_tensor(a)
+    return t.to(DEV, dtype=dtype) if dtype is not None else t.to(DEV)
+
+
+@pytest.mark.parametrize("kind", ["frac", "neg", "int", "jitter"])
+def test_adjoint_and_shear_grad_match_oracle(kind):
+    _say(f"backward parity: {kind}")
+    rng = np.random.default_rng(3)
+    n, r, c = 23, 17, 301
+    s = synth.blob_stack((n, r, c), 40, 5, dtype="f32").numpy()
+    if kind == "frac":
+        off = oracle.offsets_uniform(n, 2.6458)
+    elif kind == "neg":
+        off = oracle.offsets_uniform(n, -3.3166)
+    elif kind == "int":
+        off = np.arange(n, dtype=np.float64) * 4.0
+    else:
+        off = np.cumsum(np.r_[0.0, rng.uniform(0.2, 5.0, n - 1)])
+    b, w = oracle.frame(off, c)
+    gd = rng.uniform(-1, 1, (n, r, w)).astype(np.float32)
+    ref_gi = oracle.adjoint(gd, off, b, c)
+    ref_gi64 = oracle.adjoint(np.abs(gd), off, b, c, as_f64=True)     # magnitude bound
+    ref_go = oracle.shear_grad(s, gd, off, b)
+    gi, go = dsk.backward(_dev(s), _dev(gd), _dev(off), b)
+    torch.cuda.synchronize()
+    gi = gi.cpu().numpy().astype(np.float64)
+    if kind == "int":
+        assert gi.astype(np.float32).tobytes() == ref_gi.tobytes()
+    err = np.abs(gi - ref_gi.astype(np.float64))
+    assert (err <= 1e-5 * ref_gi64 + 1e-30).all()
+    # shear gradient: FP64 sums of the same products in another order
+    bound = 2.0 * np.abs(s).max() * np.abs(gd).astype(np.float64).sum(axis=(1, 2))
+    assert (np.abs(go.cpu().numpy() - ref_go) <= 1e-9 * bound).all()
+    # the separate entry points agree with the fused one
+    gi2 = dsk.adjoint(_dev(gd), _dev(off), b, c)
+    go2 = dsk.shear_grad(_dev(s), _dev(gd), _dev(off), b)
+    assert np.array_equal(gi2.cpu().numpy().astype(np.float64), gi)
+    assert torch.equal(go2, go)
+
+
+@pytest.fixture(scope="module")
+def cfg4():
+    _say("config 4: generating 256x512x1024 float32 stack")
+    st = synth.blob_stack((N4, R4, C4), 2000, 4, device=DEV, dtype="f32")
+    torch.cuda.synchronize()
+    off30 = oracle.offsets_uniform(N4, oracle.shift_px(30.0, STEP, PIXEL))
+    b, w = oracle.frame(off30, C4)
+    assert (b, w) == (0, W4)
+    return st, st.cpu().numpy()
+
+
+def test_config4_adjoint_and_grad_full_size(cfg4):
+    st, sn = cfg4
+    off = oracle.offsets_uniform(N4, oracle.shift_px(30.0, STEP, PIXEL))
+    gd = synth.uniform_f32((N4, R4, W4), 11, device=DEV) - 0.5
+    _say("config 4: backward kernel")
+    gi, go = dsk.backward(st, gd, _dev(off), 0)
+    torch.cuda.synchronize()
+    gdn = gd.cpu().numpy()
+    _say("config 4: oracle adjoint")
+    ref_gi = oracle.adjoint(gdn, off, 0, C4)
+    bound = oracle.adjoint(np.abs(gdn), off, 0, C4, as_f64=True)
+    err = np.abs(gi.cpu().numpy().astype(np.float64) - ref_gi)
+    assert (err <= 1e-5 * bound + 1e-30).all()
+    _say("config 4: oracle shear gradient")
+    ref_go = oracle.shear_grad(sn, gdn, off, 0)
+    bound = 2.0 * np.abs(sn).max() * np.abs(gdn).astype(np.float64).sum(axis=(1, 2))
+    assert (np.abs(go.cpu().numpy() - ref_go) <= 1e-9 * bound).all()
+
+
+def test_dot_product_adjoint_config4():
+    """<A x, y> = <x, A^T y> with x, y ~ U[0,1), FP64 reductions."""
+    _say("config 4: dot-product test")
+    x = synth.uniform_f32((N4, R4, C4), 21, device=DEV)
+    y = synth.uniform_f32((N4, R4, W4), 22, device=DEV)
+    off = _dev(oracle.offsets_uniform(N4, oracle.shift_px(30.0, STEP, PIXEL)))
+    ax = dsk.deskew(x, offsets=off, origin=0, width=W4, psum=False, pmax=False)["vol"]
+    aty = dsk.adjoint(y, off, 0, C4)
+    lhs = float((ax.double() * y.double()).sum())
+    rhs = float((x.double() * aty.double()).sum())
+    denom = float(ax.double().norm()) * float(y.double().norm())
+    assert abs(lhs - rhs) / denom <= 1e-6
+
+
+def _plane_loss64(stack_np, off, i, gt64):
+    d = oracle.deskew(stack_np[i:i + 1], off[i:i + 1], origin=0, width=W4, vol64=True)["vol64"]
+    return 0.5 * float(((d[0] - gt64[0]) ** 2).sum())
+
+
+def test_shear_grad_finite_differences(cfg4):
+    """GPU d(loss)/d(o_n) against central differences (h = 1e-3 px) of the
+    FP64 oracle loss, on planes away from integer offsets (the loss is
+    piecewise quadratic in o_n, so the difference is exact to rounding), and
+    against differences of the GPU forward itself.  The latter is loose
+    (1e-2): a plane's loss is ~1e9 while 2*h*dL/do is ~1e4, so the float32
+    rounding of the volume and of the weights dominates that quotient."""
+    st, sn = cfg4
+    off = oracle.offsets_uniform(N4, oracle.shift_px(30.0, STEP, PIXEL))
+    off_gt = oracle.offsets_uniform(N4, oracle.shift_px(32.0, STEP, PIXEL))
+    planes = [3, 17, 64, 128, 201]
+    h = 1e-3
+    vol = dsk.deskew(st, offsets=off, origin=0, width=W4, psum=False, pmax=False)["vol"]
+    gt = {}
+    for i in planes:
+        gt[i] = oracle.deskew(sn[i:i + 1], off_gt[i:i + 1], origin=0, width=W4,
+                              vol64=True)["vol64"]
+    # gD = D - GT on the chosen planes only (others zero): dL/do_n for them
+    gd = torch.zeros_like(vol)
+    for i in planes:
+        gd[i] = vol[i] - _dev(gt[i][0], torch.float32)
+    _, go = dsk.backward(st, gd, _dev(off), 0, grad_in=False)
+    go = go.cpu().numpy()
+    for i in planes:
+        frac = off[i] - math.floor(off[i])
+        assert 0.01 <= frac <= 0.99
+        op, om = off.copy(), off.copy()
+        op[i] += h
+        om[i] -= h
+        fd64 = (_plane_loss64(sn, op, i, gt[i]) - _plane_loss64(sn, om, i, gt[i])) / (2 * h)
+        assert go[i] == pytest.approx(fd64, rel=1e-4)
+        lp = dsk.deskew(st[i:i + 1].contiguous(), offsets=op[i:i + 1], origin=0, width=W4,
+                        psum=False, pmax=False)["vol"]
+        lm = dsk.deskew(st[i:i + 1].contiguous(), offsets=om[i:i + 1], origin=0, width=W4,
+                        psum=False, pmax=False)["vol"]
+        g64 = _dev(gt[i])
+        fd32 = (0.5 * float(((lp.double() - g64) ** 2).sum())
+                - 0.5 * float(((lm.double() - g64) ** 2).sum())) / (2 * h)
+        assert go[i] == pytest.approx(fd32, rel=1e-2)
+
+
+def test_autograd_chain_rule_to_angle(cfg4):
+    st, _ = cfg4
+    angle = torch.tensor(30.7, dtype=torch.float64, device=DEV, requires_grad=True)
+    offs = ag.offsets_from_angle(angle, N4, STEP, PIXEL)
+    tgt = dsk.deskew(st, offsets=ag.offsets_from_angle(torch.tensor(31.0, dtype=torch.float64,
+                                                                     device=DEV), N4, STEP,
+                                                        PIXEL),
+                     origin=0, width=W4, psum=False, pmax=False)["vol"]
+    vol = ag.deskew_volume(st, offs, 0, W4)
+    loss = 0.5 * (vol.double() - tgt.double()).pow(2).sum()
+    loss.backward()
+    _, go = dsk.backward(st, (vol - tgt).contiguous(), offs.detach(), 0, grad_in=False)
+    a = math.radians(30.7)
+    dodalpha = -np.arange(N4) * STEP * math.sin(a) / PIXEL * (math.pi / 180.0)
+    expect = float((go.cpu().numpy() * dodalpha).sum())
+    assert float(angle.grad) == pytest.approx(expect, rel=1e-9)
+    # gradient with respect to the stack is the adjoint of the residual
+    st2 = st[:8].clone().requires_grad_(True)
+    v2 = ag.deskew_volume(st2, offs.detach()[:8], 0, W4)
+    (v2 * tgt[:8]).sum().backward()
+    assert torch.equal(st2.grad, dsk.adjoint(tgt[:8].contiguous(), offs.detach()[:8], 0, C4))
+
+
+def test_calibration_recovers_32_degrees(cfg4):
+    st, sn = cfg4
+    _say("calibration: oracle ground truth at 32 deg")
+    off_gt = oracle.offsets_uniform(N4, oracle.shift_px(32.0, STEP, PIXEL))
+    gt = oracle.deskew(sn, off_gt, origin=0, width=W4)["vol"]
+    target = _dev(gt)
+    del gt
+    _say("calibration: optimising from 30 deg")
+    angle, hist = ag.calibrate_angle(st, target, 30.0, STEP, PIXEL, 0, W4)
+    _say(f"calibration: {angle:.6f} deg after {len(hist)} iterations")
+    assert abs(angle - 32.0) <= 0.01
+    assert hist[-1][1] < 1e-3 * hist[0][1]

@@ -1,0 +1,78 @@
+"""Serving loop on the GPU: every result is bitwise the same alone and in the
+mix of overlapping, batched requests; the memory budget holds."""
+import pytest
+import torch
+
+import paper_2211_00645_amd as dsk
+from paper_2211_00645_amd import synth
+from paper_2211_00645_amd.serving import GPUExecutor, Request, Scheduler, run_plain, summarize
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SHAPES = [(64, 128), (128, 256)]      # (rows, cols) of the small test pool
+MAXP = 60
+
+
+@pytest.fixture(scope="module")
+def pool():
+    p = {}
+    for k, (r, c) in enumerate(SHAPES):
+        for ch in range(2):
+            p[(r, c, ch)] = synth.blob_stack((MAXP, r, c), 40, 10 * k + ch, device=DEV)
+    torch.cuda.synchronize()
+    return p
+
+
+def _trace(n, rate, seed):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, n))
+    t -= t[0]
+    out = []
+    for i in range(n):
+        r, c = SHAPES[int(rng.integers(0, len(SHAPES)))]
+        out.append(Request(rid=i, t_arrival=float(t[i]), planes=int(rng.integers(20, MAXP + 1)),
+                           rows=r, cols=c, channels=2,
+                           angle_deg=float(rng.choice([30.0, 35.0, 45.0]))))
+    return out
+
+
+def _check_alone(pool, reqs):
+    for r in reqs:
+        assert r.status == "done", r
+        for ch in range(2):
+            stack = pool[(r.rows, r.cols, ch)][:r.planes]
+            solo = dsk.deskew(stack, r.angle_deg, r.step_um, r.pixel_um)
+            torch.cuda.synchronize()
+            got = r.result[ch]
+            assert torch.equal(got["psum"], solo["psum"].cpu()), (r.rid, ch)
+            assert torch.equal(got["pmax"], solo["pmax"].cpu()), (r.rid, ch)
+            assert torch.equal(got["vol"], solo["vol"]), (r.rid, ch)
+
+
+def test_mixed_requests_equal_solo_runs(pool):
+    reqs = _trace(24, 3000.0, 1)          # a burst: requests overlap on the GPU
+    ex = GPUExecutor(pool, n_slots=3)
+    ex.keep_results = True
+    sch = Scheduler(ex, budget_bytes=1 << 34, n_slots=3, max_batch=4)
+    done = sch.run(reqs)
+    s = summarize(done)
+    print(f"serving: {s} launches={sch.launches} max_inflight={sch.max_inflight}", flush=True)
+    assert s["done"] == 24
+    assert sch.launches < 24              # requests were batched
+    _check_alone(pool, done)
+
+
+def test_budget_holds_and_plain_baseline(pool):
+    reqs = _trace(10, 5000.0, 2)
+    ex = GPUExecutor(pool, n_slots=4)
+    ex.keep_results = True
+    from paper_2211_00645_amd.serving import request_bytes
+    one = max(request_bytes(r, ex.width(r)) for r in reqs)
+    sch = Scheduler(ex, budget_bytes=2 * one, n_slots=4, max_batch=8)
+    done = sch.run(reqs)
+    assert all(r.status == "done" for r in done)
+    assert sch.peak_used <= sch.budget and sch.used == 0
+    _check_alone(pool, done)
+    plain = run_plain(GPUExecutor(pool, n_slots=1), _trace(10, 5000.0, 2))
+    assert all(r.status == "done" for r in plain)
