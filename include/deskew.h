@@ -210,6 +210,35 @@ int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host,
                     void *table_dev, size_t table_bytes, const dsk_tune *tune,
                     hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Rolling update (methods section, rolling update mode; Fig. 4a): for dim
+ * samples the displayed projection is refreshed after every camera image
+ * instead of once per stack.  State (all DEVICE, caller-owned):
+ *   vol    [planes][rows][width] float32 -- the current deskewed images;
+ *   tree   dsk_rolling_tree_bytes(d, width) bytes -- a max-tree over images
+ *          (NULL allowed when planes == 1);
+ *   sum64  [rows][width] double -- the running FP64 sum;
+ *   psum, pmax [rows][width] float32 -- the displayed projections.
+ * dsk_rolling_reset zeroes all of it (an empty stack: every image 0).
+ * dsk_rolling_update_u16 remaps raw image n ([rows][cols] uint16, DEVICE)
+ * at offset o[n] (offsets_dev, or n * shift_px when NULL) into leaf n,
+ * adds (new - old) to sum64 and refreshes the maximum along the tree; psum
+ * and pmax then equal the projections of the stack made of the latest image
+ * at every index (pmax bitwise; psum equal to a forward pass when each
+ * image has been written once, in order).  One kernel per image.
+ * ------------------------------------------------------------------- */
+size_t dsk_rolling_tree_bytes(dsk_dims d, int64_t out_width);
+
+int dsk_rolling_reset(dsk_dims d, int64_t out_width, float *vol, float *tree,
+                      double *sum64, float *psum, float *pmax,
+                      hipStream_t stream);
+
+int dsk_rolling_update_u16(const uint16_t *plane, int32_t n, dsk_dims d,
+                           const double *offsets_dev, double shift_px,
+                           int64_t origin, int64_t out_width, float *vol,
+                           float *tree, double *sum64, float *psum,
+                           float *pmax, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,10 @@ _SIGS = {
     "dsk_batch_get_tune": (ctypes.c_int, [c_vp, ctypes.POINTER(Tune), ctypes.POINTER(c_dbl)]),
     "dsk_batch_destroy": (ctypes.c_int, [c_vp]),
     "dsk_jobs_table_bytes": (c_sz, [ctypes.c_int]),
+    "dsk_rolling_tree_bytes": (c_sz, [Dims, c_i64]),
+    "dsk_rolling_reset": (ctypes.c_int, [Dims, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "dsk_rolling_update_u16": (ctypes.c_int, [c_vp, c_i32, Dims, c_vp, c_dbl, c_i64, c_i64,
+                                              c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "dsk_jobs_launch": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int, c_vp, c_vp, c_sz,
                                        ctypes.POINTER(Tune), c_vp]),
 }

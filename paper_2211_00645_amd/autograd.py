@@ -85,19 +85,52 @@ def minimise_angle(loss_and_grad, angle0_deg: float, iters: int = 300, lr: float
     return a, hist
 
 
+def calibrate_stages(n_planes: int, first: int = 8):
+    """Plane counts of the coarse-to-fine calibration: first, 2*first, ...,
+    n_planes.  A shift error grows linearly with the plane index, so the
+    first planes stay within a pixel of alignment for a wide range of
+    angles; each doubling halves the angle range it can correct."""
+    ks, k = [], max(2, min(first, n_planes))
+    while k < n_planes:
+        ks.append(k)
+        k *= 2
+    ks.append(n_planes)
+    return ks
+
+
+def calibrate_with(loss_and_grad_k, n_planes: int, angle0_deg: float, lr0: float = 0.5,
+                   first: int = 8, tol_deg: float = 1e-4, iters: int = 200):
+    """Coarse-to-fine angle calibration driven by ``loss_and_grad_k(angle,
+    k) -> (L, dL/dangle)`` restricted to the first k planes.  Each stage runs
+    ``minimise_angle`` from the previous estimate with a step that shrinks
+    with k.  Returns (angle, history over all stages)."""
+    a = float(angle0_deg)
+    hist = []
+    ks = calibrate_stages(n_planes, first)
+    for i, k in enumerate(ks):
+        lr = lr0 * ks[0] / k
+        tol = tol_deg if i == len(ks) - 1 else lr / 64.0
+        a, h = minimise_angle(lambda x: loss_and_grad_k(x, k), a, iters=iters, lr=lr,
+                              tol_deg=tol)
+        hist.extend(h)
+    return a, hist
+
+
 def calibrate_angle(stack: torch.Tensor, target: torch.Tensor, angle0_deg: float,
                     step_um: float, pixel_um: float, origin: int, width: int,
-                    iters: int = 300, lr: float = 0.05, tol_deg: float = 1e-4):
+                    first: int = 8, lr0: float = 0.5, tol_deg: float = 1e-4):
     """Recover the sheet angle whose deskew of ``stack`` best matches
     ``target`` in least squares, by gradient descent through the adjoint:
     the loss gradient reaches alpha via the per-image shear gradient and
-    Eq. 1.  Returns (angle_deg, history)."""
-    def loss_and_grad(a):
+    Eq. 1.  Coarse to fine over the number of planes (``calibrate_with``).
+    Returns (angle_deg, history)."""
+    def loss_and_grad_k(a, k):
         angle = torch.tensor(a, dtype=torch.float64, device=stack.device, requires_grad=True)
-        offs = offsets_from_angle(angle, stack.shape[0], step_um, pixel_um)
-        vol = deskew_volume(stack, offs, origin, width)
-        loss = 0.5 * (vol.double() - target.double()).pow(2).sum()
+        offs = offsets_from_angle(angle, k, step_um, pixel_um)
+        vol = deskew_volume(stack[:k], offs, origin, width)
+        loss = 0.5 * (vol.double() - target[:k].double()).pow(2).sum()
         loss.backward()
         return float(loss.detach()), float(angle.grad)
 
-    return minimise_angle(loss_and_grad, angle0_deg, iters=iters, lr=lr, tol_deg=tol_deg)
+    return calibrate_with(loss_and_grad_k, stack.shape[0], angle0_deg, lr0=lr0, first=first,
+                          tol_deg=tol_deg)

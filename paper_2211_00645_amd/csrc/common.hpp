@@ -33,7 +33,7 @@ inline bool tune_ok(const dsk_tune &t) {
 inline bool vec_ok(const dsk_tune &t, dsk_dims d, int64_t width, const void *in, int in_is_f32,
                    const float *vol) {
     if (t.per_thread < 4) return false;
-    if ((int64_t)d.planes * d.rows * d.cols < 64) return false;
+    if ((int64_t)d.planes * d.rows * d.cols < 64 || (int64_t)d.rows * d.cols < 8) return false;
     if (width >= (int64_t(1) << 27) || d.cols >= (1 << 27)) return false;
     if (((int64_t)d.rows * width) % 4 != 0 || ((int64_t)d.rows * d.cols) % 4 != 0) return false;
     const uintptr_t ia = in_is_f32 ? 15 : 7;

@@ -204,32 +204,34 @@ __device__ __forceinline__ void store_f32x4(float *p, f32x4 v) {
         *(f32x4 *)p = v;
 }
 
-// Raw source window of one 4-column group: 8 uint16 (16 bytes) starting at
-// a 4-aligned element, or 5 floats starting at the first needed element.
+// Raw source window of one 4-column group: the 8 uint16 (16 bytes) starting
+// at the 4-aligned element `off` before the first needed pixel, or the 5
+// floats starting at that pixel (`off + sh`).
 template <typename TIn>
 struct RawWin;
 
 template <>
 struct RawWin<uint16_t> {
     uint4 q;
-    // sh: position of the first needed element inside the aligned window
-    __device__ __forceinline__ void load(const uint16_t *row, int p, int sh) {
-        __builtin_memcpy(&q, row + (p - sh), sizeof(q));   // 8-byte aligned
+    __device__ __forceinline__ void load(const uint16_t *row, int off, int) {
+        __builtin_memcpy(&q, row + off, sizeof(q));   // 8-byte aligned
     }
+    // The five pixels starting at element sh (0..3) of the window, without
+    // branches: pick the dword pair, then a 0/16-bit funnel shift.
     __device__ __forceinline__ void extract(int sh, float v[5]) const {
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
-#define DSK_LO(e) (float)(w[(e) >> 1] & 0xffffu)
-#define DSK_HI(e) (float)(w[(e) >> 1] >> 16)
-#define DSK_EL(e) (((e)&1) ? DSK_HI(e) : DSK_LO(e))
-        switch (sh) {
-        case 0: v[0] = DSK_EL(0); v[1] = DSK_EL(1); v[2] = DSK_EL(2); v[3] = DSK_EL(3); v[4] = DSK_EL(4); break;
-        case 1: v[0] = DSK_EL(1); v[1] = DSK_EL(2); v[2] = DSK_EL(3); v[3] = DSK_EL(4); v[4] = DSK_EL(5); break;
-        case 2: v[0] = DSK_EL(2); v[1] = DSK_EL(3); v[2] = DSK_EL(4); v[3] = DSK_EL(5); v[4] = DSK_EL(6); break;
-        default: v[0] = DSK_EL(3); v[1] = DSK_EL(4); v[2] = DSK_EL(5); v[3] = DSK_EL(6); v[4] = DSK_EL(7); break;
-        }
-#undef DSK_EL
-#undef DSK_HI
-#undef DSK_LO
+        const bool hi = sh >= 2;
+        const uint32_t e0 = hi ? q.y : q.x;
+        const uint32_t e1 = hi ? q.z : q.y;
+        const uint32_t e2 = hi ? q.w : q.z;
+        const uint32_t b = (uint32_t)(sh & 1) * 16u;
+        const uint32_t a0 = __builtin_amdgcn_alignbit(e1, e0, b);
+        const uint32_t a1 = __builtin_amdgcn_alignbit(e2, e1, b);
+        const uint32_t a2 = e2 >> b;
+        v[0] = (float)(a0 & 0xffffu);
+        v[1] = (float)(a0 >> 16);
+        v[2] = (float)(a1 & 0xffffu);
+        v[3] = (float)(a1 >> 16);
+        v[4] = (float)(a2 & 0xffffu);
     }
 };
 
@@ -237,9 +239,9 @@ template <>
 struct RawWin<float> {
     float4 a;
     float b;
-    __device__ __forceinline__ void load(const float *row, int p, int) {
-        __builtin_memcpy(&a, row + p, sizeof(a));   // 4-byte aligned
-        b = row[p + 4];
+    __device__ __forceinline__ void load(const float *row, int off, int sh) {
+        __builtin_memcpy(&a, row + off + sh, sizeof(a));   // 4-byte aligned
+        b = row[off + sh + 4];
     }
     __device__ __forceinline__ void extract(int, float v[5]) const {
         v[0] = a.x;
@@ -252,28 +254,58 @@ struct RawWin<float> {
 
 // One vector tile: row r, columns [x0, x0 + 4*BLOCK*G).  Thread t owns the
 // 4-column groups starting at x0 + 4*(t + BLOCK*g).
-template <typename TIn, int BLOCK, int G, bool NT>
+//
+// Planes are handled in chunks of 64.  For a chunk, lane l of every
+// wavefront computes plane (c0 + l)'s coefficients, its window offset and,
+// per group, whether the wavefront's 256 columns read entirely inside the
+// raw row (IN), entirely outside it (OUT: padding) or across an end (EDGE).
+// A chunk whose planes are all IN (or all OUT) for a group runs a tight loop
+// with no per-plane classification; the per-plane values come from the
+// chunk lanes by readlane.  The scalar unit is shared by all wavefronts of
+// a compute unit, so per-plane uniform work is kept to a few instructions.
+template <typename TIn, int BLOCK, int G, int UNR, bool NT>
 struct VecTile {
     static constexpr int T = 4 * BLOCK * G;
     enum { OUT = 0, IN = 1, EDGE = 2 };
     const FwdArgs<TIn> &a;
-    int r, W, C, x0, wv;
-    int64_t total;
+    int r, W, C, N, x0, wv, gmod, lane, lane4;
+    // source window offsets (from the row start, in elements) that keep a
+    // 4-aligned 8-element window inside the stack, away from its two ends
+    int lo_off, hi_off;
+    int first_special, last_special;   // planes whose row lies at a stack end
+    int64_t rstep, ostep, total;
+    const TIn *rp0;                    // row r of plane 0
+    float *op0;                        // volume row r of plane 0 (or null)
     bool full[G], wfull[G];
     double acc[G][4];
     float mx[G][4];
-    CoefCache cc;
+    // chunk lane data (plane c0 + lane)
+    int ls0, lobsh;                    // window start s0, and (s0 - sh) * 4 + sh
+    float lwlo, lwhi;
 
     __device__ __forceinline__ VecTile(const FwdArgs<TIn> &args, int row, int x0_)
-        : a(args), r(row), W((int)args.W), C(args.C), x0(x0_) {
-        total = (int64_t)a.N * a.R * C;
+        : a(args), r(row), W((int)args.W), C(args.C), N(args.N), x0(x0_) {
+        total = (int64_t)N * a.R * C;
+        rstep = (int64_t)a.R * C;
+        ostep = (int64_t)a.R * W;
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+        lane = (int)threadIdx.x & 63;
+        lane4 = 4 * lane;
+        // rows*C is a multiple of 4, so every plane's row start has this residue
+        gmod = (int)(((int64_t)r * C) & 3);
+        lo_off = -8 + ((-gmod) & 3);
+        hi_off = C - 1 - ((C - 1 + gmod) & 3);
+        // rows*C >= 8: only plane 0 can start closer than 8 elements to the
+        // stack start and only plane N-1 can end closer than 8 to its end
+        first_special = ((int64_t)r * C < 8) ? 0 : -1;
+        last_special = ((int64_t)(N - 1) * rstep + (int64_t)r * C + C + 8 > total) ? N - 1 : -1;
+        rp0 = a.in + (int64_t)r * C;
+        op0 = a.vol ? a.vol + (int64_t)r * W : nullptr;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int xg = x0 + 4 * ((int)threadIdx.x + BLOCK * g);
             full[g] = xg >= 0 && xg + 4 <= W;
-            // every group of this wavefront is whole
-            const int w0 = x0 + 4 * (64 * wv + BLOCK * g);
+            const int w0 = x0 + cg(g);
             wfull[g] = w0 >= 0 && w0 + 256 <= W;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
@@ -281,16 +313,47 @@ struct VecTile {
                 mx[g][i] = -__builtin_huge_valf();
             }
         }
-        cc.init(a.offs, a.shift, a.origin, a.N);
     }
 
-    __device__ __forceinline__ int xg(int g) const {
-        return x0 + 4 * ((int)threadIdx.x + BLOCK * g);
+    __device__ __forceinline__ int cg(int g) const { return 4 * (64 * wv + BLOCK * g); }
+    __device__ __forceinline__ int xg(int g) const { return x0 + 4 * ((int)threadIdx.x + BLOCK * g); }
+
+    // Class of the wavefront's group g for window start s0: its positions are
+    // [s0 + cg, s0 + cg + 257).
+    __device__ __forceinline__ int cls_of(int s0, int g) const {
+        const int q = s0 + cg(g);
+        if (q >= 0 && q + 257 <= C) return IN;
+        if (q + 257 <= 0 || q >= C) return OUT;
+        return EDGE;
+    }
+
+    __device__ __forceinline__ void chunk(int c0) {
+        const int n = min(c0 + lane, N - 1);
+        double o;
+        if (a.offs) {
+            o = a.offs[n];
+            // consume the load here so the wait for it stays on this path
+            asm volatile("" ::"v"(o));
+        } else {
+            o = __dmul_rn((double)n, a.shift);
+        }
+        const PlaneCoef pc = coef_from_offset(o, a.origin);
+        // window start; beyond +-2^28 every position lies outside the row
+        // (rows and widths of this kernel are below 2^27), so clamp there
+        const int s0l = x0 - pc.k - 1;
+        const int s0 = s0l < -(1 << 28) ? -(1 << 28) : (s0l > (1 << 28) ? (1 << 28) : s0l);
+        const int sh = (gmod + s0) & 3;
+        ls0 = s0;
+        lobsh = (s0 - sh) * 4 + sh;
+        lwlo = pc.wlo;
+        lwhi = pc.whi;
     }
 
     __device__ __forceinline__ void store(float *orow, int g, const float d[4]) const {
         float *o = orow + xg(g);
-        if (wfull[g] || full[g]) {
+        if (wfull[g]) {                  // uniform: the whole wavefront is inside the row
+            store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
+        } else if (full[g]) {
             store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
         } else {
 #pragma unroll
@@ -299,84 +362,129 @@ struct VecTile {
         }
     }
 
-    // Planes [n0, n0 + U): loads of all U planes first, then interpolation.
+    __device__ __forceinline__ void interp(int g, const float v[5], float wlo, float whi,
+                                           float d[4]) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            d[i] = fmaf(whi, v[i + 1], wlo * v[i]);
+            acc[g][i] += (double)d[i];
+            mx[g][i] = fmaxf(mx[g][i], d[i]);
+        }
+    }
+
+    // U planes from chunk lane li0, all inside the row for group g.
     template <int U>
-    __device__ __forceinline__ void planes(int n0) {
-        RawWin<TIn> raw[U][G];
-        PlaneCoef pc[U];
-        const TIn *row[U];
-        int s0[U], sh[U], cls[U][G];
-        bool moved[U][G];
+    __device__ __forceinline__ void step_in(int g, int li0, const TIn *&rp, float *&op) {
+        RawWin<TIn> raw[U];
+        int sh[U];
+        float wlo[U], whi[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int n = n0 + u;
-            pc[u] = cc.get(n);
-            const int64_t grow = ((int64_t)n * a.R + r) * C;
-            row[u] = a.in + grow;
-            // window start; beyond +-2^28 every position lies outside the row
-            // (rows and widths of this kernel are below 2^27), so clamp there
-            const int s0l = x0 - pc[u].k - 1;
-            s0[u] = s0l < -(1 << 28) ? -(1 << 28) : (s0l > (1 << 28) ? (1 << 28) : s0l);
-            sh[u] = (int)((grow + s0[u]) & 3);   // same for every group
-            // window starts the stack bounds allow, relative to the row
-            const int lo_off = (int)(grow < 8 ? -grow : -8);
-            const int64_t hi64 = total - grow - 8;
-            const int hi_off = (int)(hi64 < (int64_t)C + 8 ? hi64 : (int64_t)C + 8);
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                // positions [q0, q0 + 256 + 1) of this wavefront's groups
-                const int q0 = s0[u] + 4 * (64 * wv + BLOCK * g);
-                const int q1 = q0 + 4 * 63 + 5;
-                cls[u][g] = (q0 >= 0 && q1 <= C) ? IN : ((q1 <= 0 || q0 >= C) ? OUT : EDGE);
-                const int p = s0[u] + 4 * ((int)threadIdx.x + BLOCK * g);
-                moved[u][g] = false;
-                if (cls[u][g] == IN) {
-                    raw[u][g].load(row[u], p, sh[u]);
-                } else if (cls[u][g] == EDGE) {
-                    const int off = p - sh[u];
-                    const int oc = off < lo_off ? lo_off : (off > hi_off ? hi_off : off);
-                    moved[u][g] = oc != off;
-                    raw[u][g].load(row[u], oc + sh[u], sh[u]);
-                }
-            }
+            const int v = __builtin_amdgcn_readlane(lobsh, li0 + u);
+            sh[u] = v & 3;
+            wlo[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li0 + u));
+            whi[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li0 + u));
+            raw[u].load(rp, (v >> 2) + cg(g) + lane4, sh[u]);
+            rp += rstep;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int n = n0 + u;
-            float *orow = a.vol ? a.vol + ((int64_t)n * a.R + r) * W : nullptr;
+            float v[5], d[4];
+            raw[u].extract(sh[u], v);
+            interp(g, v, wlo[u], whi[u], d);
+            if (op) {
+                store(op, g, d);
+                op += ostep;
+            }
+        }
+    }
+
+    // One plane in general position for group g (chunk lane li, plane n).
+    __device__ __forceinline__ void step_edge(int g, int li, int n, const TIn *rp, float *op) {
+        const int s0 = __builtin_amdgcn_readlane(ls0, li);
+        const int v = __builtin_amdgcn_readlane(lobsh, li);
+        const int sh = v & 3;
+        const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
+        const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
+        const int cls = cls_of(s0, g);
+        float d[4];
+        if (cls == OUT) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                d[i] = 0.0f;
+                mx[g][i] = fmaxf(mx[g][i], 0.0f);
+            }
+        } else {
+            const int p = s0 + cg(g) + lane4;
+            RawWin<TIn> raw;
+            bool moved = false;
+            if (cls == IN) {
+                raw.load(rp, p - sh, sh);
+            } else {
+                int lo = lo_off, hi = hi_off;
+                const bool special = n == first_special || n == last_special;
+                if (special) {
+                    const int64_t grow = rp - a.in;
+                    lo = (int)(-grow > (int64_t)lo ? -grow : (int64_t)lo);
+                    hi = (int)(total - 8 - grow < (int64_t)hi ? total - 8 - grow : (int64_t)hi);
+                }
+                const int off = p - sh;
+                const int oc = off < lo ? lo : (off > hi ? hi : off);
+                moved = special && oc != off;
+                raw.load(rp, oc, sh);
+            }
+            float vv[5];
+            raw.extract(sh, vv);
+            if (cls == EDGE) {
+#pragma unroll
+                for (int i = 0; i < 5; ++i)
+                    if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
+                if (moved) {
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
+                }
+            }
+            interp(g, vv, wlo, whi, d);
+        }
+        if (op) store(op, g, d);
+    }
+
+    __device__ __forceinline__ void run() {
+        for (int c0 = 0; c0 < N; c0 += 64) {
+            const int cn = min(64, N - c0);
+            chunk(c0);
+            const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < cn);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                float d[4];
-                if (cls[u][g] == OUT) {
-                    // padding: zero output, nothing to add to the sum
+                const int cl = cls_of(ls0, g);
+                const uint64_t bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
+                const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
+                const TIn *rp = rp0 + (int64_t)c0 * rstep;
+                float *op = op0 ? op0 + (int64_t)c0 * ostep : nullptr;
+                if (bin == valid) {
+                    int li = 0;
+                    for (; li + UNR <= cn; li += UNR) step_in<UNR>(g, li, rp, op);
+                    for (; li < cn; ++li) step_in<1>(g, li, rp, op);
+                } else if (bout == valid) {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        d[i] = 0.0f;
-                        mx[g][i] = fmaxf(mx[g][i], 0.0f);
-                    }
-                } else {
-                    float v[5];
-                    raw[u][g].extract(sh[u], v);
-                    if (cls[u][g] == EDGE) {
-                        const int p = s0[u] + 4 * ((int)threadIdx.x + BLOCK * g);
-#pragma unroll
-                        for (int i = 0; i < 5; ++i)
-                            if (p + i < 0 || p + i >= C) v[i] = 0.0f;
-                        if (moved[u][g]) {
-#pragma unroll
-                            for (int i = 0; i < 5; ++i) v[i] = load_px(row[u], p + i, C);
+                    for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
+                    if (op) {
+                        const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                        for (int li = 0; li < cn; ++li) {
+                            store(op, g, z);
+                            op += ostep;
                         }
                     }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        d[i] = fmaf(pc[u].whi, v[i + 1], pc[u].wlo * v[i]);
-                        acc[g][i] += (double)d[i];
-                        mx[g][i] = fmaxf(mx[g][i], d[i]);
+                } else {
+                    for (int li = 0; li < cn; ++li) {
+                        step_edge(g, li, c0 + li, rp, op);
+                        rp += rstep;
+                        if (op) op += ostep;
                     }
                 }
-                if (orow) store(orow, g, d);
             }
         }
+        finish();
     }
 
     __device__ __forceinline__ void finish() {
@@ -401,11 +509,8 @@ __device__ __forceinline__ void fwd_tile_vec(const FwdArgs<TIn> &a, int r, int t
     const int ca = (4 - m) & 3;
     const int x0 = (ca ? ca - 4 : 0) + tile * T;
     if (x0 >= a.W) return;
-    VecTile<TIn, BLOCK, G, NT> vt(a, r, x0);
-    int n = 0;
-    for (; n + UNR <= a.N; n += UNR) vt.template planes<UNR>(n);
-    for (; n < a.N; ++n) vt.template planes<1>(n);
-    vt.finish();
+    VecTile<TIn, BLOCK, G, UNR, NT> vt(a, r, x0);
+    vt.run();
 }
 
 // Plain launches: one workgroup per (row, column tile).
@@ -558,6 +663,70 @@ __global__ void k_backward_finalize(const double *__restrict__ partial, int N, i
         for (int g = 0; g < G; ++g) s += partial[(int64_t)n * G + g];
         gout[n] = s;
     }
+}
+
+// ---------------------------------------------------------------- rolling
+//
+// Rolling update (the paper's rolling display mode, Fig. 4a): after every
+// camera image the projections are refreshed.  Image n is remapped into
+// leaf n of the volume; the FP64 running sum takes the difference between
+// the new and the old leaf; the maximum is refreshed along a max-tree over
+// images (level l holds ceil(N / 2^l) nodes of R x W, node j = max of nodes
+// 2j and 2j+1 of level l-1; level 0 is the volume), since a maximum cannot be
+// un-applied.  One thread per output pixel walks its path to the root.
+
+struct RollArgs {
+    const void *plane;     // raw image n, [R][C]
+    float *vol;            // level 0: [N][R][W]
+    float *tree;           // levels 1..L concatenated
+    double *sum64;         // [R][W]
+    float *psum, *pmax;    // [R][W]
+    const double *offs;
+    double shift, origin;
+    int64_t W;
+    int32_t N, R, C, n, levels;
+};
+
+template <typename TIn>
+__global__ __launch_bounds__(256) void k_rolling_update(RollArgs a) {
+    const int64_t RW = (int64_t)a.R * a.W;
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= RW) return;
+    const int r = (int)(idx / a.W);
+    const int64_t x = idx - (int64_t)r * a.W;
+    const PlaneCoef pc = plane_coef(a.offs, a.shift, a.origin, a.n);
+    const TIn *row = (const TIn *)a.plane + (int64_t)r * a.C;
+    const int64_t i = x - pc.k;
+    const float d = fmaf(pc.whi, load_px(row, i, (int64_t)a.C), pc.wlo * load_px(row, i - 1, (int64_t)a.C));
+    float *leaf = a.vol + (int64_t)a.n * RW + idx;
+    const float old = *leaf;
+    *leaf = d;
+    const double sum = a.sum64[idx] + ((double)d - (double)old);
+    a.sum64[idx] = sum;
+    a.psum[idx] = (float)sum;
+    float m = d;
+    int j = a.n, cnt = a.N;
+    const float *below = a.vol;
+    float *lev = a.tree;
+    for (int l = 0; l < a.levels; ++l) {
+        const int sib = j ^ 1;
+        if (sib < cnt) m = fmaxf(m, below[(int64_t)sib * RW + idx]);
+        j >>= 1;
+        const int next = (cnt + 1) >> 1;
+        lev[(int64_t)j * RW + idx] = m;
+        below = lev;
+        lev += (int64_t)next * RW;
+        cnt = next;
+    }
+    a.pmax[idx] = m;
+}
+
+// Fill n floats (or doubles) with zero; a kernel, so it is safe inside a
+// captured graph.
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero(T *p, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = T(0);
 }
 
 }  // namespace dsk

@@ -107,3 +107,10 @@ def test_launch_entry_points_reject_bad_arguments_before_any_launch():
     assert lib.dsk_jobs_launch(None, 1, fake, fake, 1024, None, None) == L.DSK_EINVAL
     assert lib.dsk_batch_launch(None, None) == L.DSK_EINVAL
     assert lib.dsk_batch_destroy(None) == L.DSK_EINVAL
+
+
+def test_rolling_tree_size():
+    lib = L.lib()
+    f = lambda n: lib.dsk_rolling_tree_bytes(L.Dims(n, 3, 5), 7) // (3 * 7 * 4)
+    assert [f(1), f(2), f(3), f(5), f(8), f(512)] == [0, 1, 3, 6, 7, 511]
+    assert lib.dsk_rolling_tree_bytes(L.Dims(0, 3, 5), 7) == 0
