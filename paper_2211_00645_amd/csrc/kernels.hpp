@@ -216,6 +216,13 @@ struct RawWin<uint16_t> {
     __device__ __forceinline__ void load(const uint16_t *row, int off, int) {
         __builtin_memcpy(&q, row + off, sizeof(q));   // 8-byte aligned
     }
+    // Wait for the load here (an empty asm that reads the registers), so no
+    // load is pending across a loop back-edge: the wait counter is in-order
+    // and shared with stores, and a pending load there would make the
+    // compiler wait for every store issued since.
+    __device__ __forceinline__ void settle() const {
+        asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+    }
     // The five pixels starting at element sh (0..3) of the window, without
     // branches: pick the dword pair, then a 0/16-bit funnel shift.
     __device__ __forceinline__ void extract(int sh, float v[5]) const {
@@ -242,6 +249,9 @@ struct RawWin<float> {
     __device__ __forceinline__ void load(const float *row, int off, int sh) {
         __builtin_memcpy(&a, row + off + sh, sizeof(a));   // 4-byte aligned
         b = row[off + sh + 4];
+    }
+    __device__ __forceinline__ void settle() const {
+        asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(b));
     }
     __device__ __forceinline__ void extract(int, float v[5]) const {
         v[0] = a.x;
@@ -372,29 +382,73 @@ struct VecTile {
         }
     }
 
-    // U planes from chunk lane li0, all inside the row for group g.
+    // Issue the loads of chunk planes [li0, li0 + U) for group g (indices
+    // past the chunk end repeat its last plane: in bounds, never used).
     template <int U>
-    __device__ __forceinline__ void step_in(int g, int li0, const TIn *&rp, float *&op) {
-        RawWin<TIn> raw[U];
-        int sh[U];
-        float wlo[U], whi[U];
+    __device__ __forceinline__ void issue(int g, int li0, int cn, const TIn *rpc,
+                                          RawWin<TIn> raw[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int v = __builtin_amdgcn_readlane(lobsh, li0 + u);
-            sh[u] = v & 3;
-            wlo[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li0 + u));
-            whi[u] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li0 + u));
-            raw[u].load(rp, (v >> 2) + cg(g) + lane4, sh[u]);
-            rp += rstep;
+            const int li = min(li0 + u, cn - 1);
+            const int v = __builtin_amdgcn_readlane(lobsh, li);
+            raw[u].load(rpc + (int64_t)li * rstep, (v >> 2) + cg(g) + lane4, v & 3);
         }
+    }
+
+    // Chunk planes [0, cn) all inside the row for group g, with every
+    // column of this wavefront inside the frame (wfull), software-pipelined:
+    // the loads of the next U planes go out before the current U planes are
+    // interpolated and stored, and are waited for after those stores.  Each
+    // plane issues exactly one 16-byte store per lane (no branch around it),
+    // so the compiler can count the stores and the wait for the loads leaves
+    // them in flight: stores never hold up the plane loop.
+    template <int U, bool VOL>
+    __device__ __forceinline__ void in_loop(int g, int cn, const TIn *rpc, float *op) {
+        const int groups = cn / U;
+        float *o = VOL ? op + xg(g) : nullptr;
+        if (groups > 0) {
+            RawWin<TIn> cur[U];
+            issue<U>(g, 0, cn, rpc, cur);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            float v[5], d[4];
-            raw[u].extract(sh[u], v);
-            interp(g, v, wlo[u], whi[u], d);
-            if (op) {
-                store(op, g, d);
-                op += ostep;
+            for (int u = 0; u < U; ++u) cur[u].settle();
+            for (int gi = 0; gi < groups; ++gi) {
+                RawWin<TIn> nxt[U];
+                issue<U>(g, (gi + 1) * U, cn, rpc, nxt);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int li = gi * U + u;
+                    const int v = __builtin_amdgcn_readlane(lobsh, li);
+                    const float wlo =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
+                    const float whi =
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
+                    float vv[5], d[4];
+                    cur[u].extract(v & 3, vv);
+                    interp(g, vv, wlo, whi, d);
+                    if constexpr (VOL) {
+                        store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
+                        o += ostep;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    nxt[u].settle();
+                    cur[u] = nxt[u];
+                }
+            }
+        }
+        for (int li = groups * U; li < cn; ++li) {
+            RawWin<TIn> one[1];
+            issue<1>(g, li, cn, rpc, one);
+            const int v = __builtin_amdgcn_readlane(lobsh, li);
+            const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
+            const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
+            float vv[5], d[4];
+            one[0].extract(v & 3, vv);
+            interp(g, vv, wlo, whi, d);
+            if constexpr (VOL) {
+                store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
+                o += ostep;
             }
         }
     }
@@ -461,10 +515,11 @@ struct VecTile {
                 const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
                 const TIn *rp = rp0 + (int64_t)c0 * rstep;
                 float *op = op0 ? op0 + (int64_t)c0 * ostep : nullptr;
-                if (bin == valid) {
-                    int li = 0;
-                    for (; li + UNR <= cn; li += UNR) step_in<UNR>(g, li, rp, op);
-                    for (; li < cn; ++li) step_in<1>(g, li, rp, op);
+                if (bin == valid && wfull[g]) {
+                    if (op)
+                        in_loop<UNR, true>(g, cn, rp, op);
+                    else
+                        in_loop<UNR, false>(g, cn, rp, op);
                 } else if (bout == valid) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
