@@ -54,6 +54,7 @@ int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out)
         const dsk_job &j = jobs[i];
         const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol);
         const int64_t tx = tiles_x(j.out_width, t, vec);
+        const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec);
         if (tx > kMaxI32) return -1;
         JobDev r;
         r.in = j.in;
@@ -70,9 +71,9 @@ int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out)
         r.C = j.dims.cols;
         r.tiles_x = (int32_t)tx;
         r.vec = vec ? 1 : 0;
-        r.pad_ = 0;
+        r.edge_blocks = (int32_t)eb;
         out[i] = r;
-        begin += tx * j.dims.rows;
+        begin += tx * j.dims.rows + eb;
         if (begin < 0 || begin > (int64_t(1) << 50)) return -1;
     }
     return begin;

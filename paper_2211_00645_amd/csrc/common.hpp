@@ -42,11 +42,23 @@ inline bool vec_ok(const dsk_tune &t, dsk_dims d, int64_t width, const void *in,
     return true;
 }
 
-// Column tiles of one output row.  The vector kernel's first tile starts up
-// to 3 columns left of 0, so it may need one more tile.
+// Column tiles of one output row.  The vector kernel tiles the row's whole
+// 4-aligned groups (at most W/4 of them); the scalar kernel tiles columns.
 inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec) {
     const int64_t tile = (int64_t)t.block * t.per_thread;
-    return (width + (vec ? 3 : 0) + tile - 1) / tile;
+    if (vec) {
+        const int64_t groups = width / 4, per = tile / 4;
+        const int64_t n = (groups + per - 1) / per;
+        return n > 0 ? n : 1;
+    }
+    return (width + tile - 1) / tile;
+}
+
+// Workgroups of the vector kernel for the rows' unaligned edge columns
+// (none when the width is a multiple of 4): one lane per (row, slot of 6).
+inline int64_t edge_blocks(dsk_dims d, int64_t width, const dsk_tune &t, bool vec) {
+    if (!vec || width % 4 == 0) return 0;
+    return (6 * (int64_t)d.rows + t.block - 1) / t.block;
 }
 
 template <int V>

@@ -62,25 +62,28 @@ extern "C" int dsk_plan(dsk_dims d, const double *offsets_px, double shift_px,
 namespace dsk {
 
 template <typename TIn, int B, int PT, int U, bool NT>
-static hipError_t fwd_launch(const FwdArgs<TIn> &a, bool vec, int64_t tiles, hipStream_t s) {
-    const dim3 grid((unsigned)(tiles * a.R)), block(B);
+static hipError_t fwd_launch(const FwdArgs<TIn> &a, bool vec, int64_t tiles, int64_t edge,
+                             hipStream_t s) {
+    const dim3 block(B);
     if constexpr (PT >= 4) {
         if (vec) {
+            const dim3 grid((unsigned)(tiles * a.R + edge));
             hipLaunchKernelGGL((k_forward_vec<TIn, B, PT / 4, U, NT>), grid, block, 0, s, a,
                                (int)tiles);
             return hipGetLastError();
         }
     }
-    hipLaunchKernelGGL((k_forward_scalar<TIn, B, PT, NT>), grid, block, 0, s, a, (int)tiles);
+    hipLaunchKernelGGL((k_forward_scalar<TIn, B, PT, NT>), dim3((unsigned)(tiles * a.R)), block,
+                       0, s, a, (int)tiles);
     return hipGetLastError();
 }
 
 template <typename TIn>
 static hipError_t fwd_dispatch(const FwdArgs<TIn> &a, const dsk_tune &t, bool vec, int64_t tiles,
-                               hipStream_t s) {
+                               int64_t edge, hipStream_t s) {
     return dispatch_tune(t, [&](auto B, auto P, auto U, auto NT) {
         return fwd_launch<TIn, decltype(B)::value, decltype(P)::value, decltype(U)::value,
-                          decltype(NT)::value>(a, vec, tiles, s);
+                          decltype(NT)::value>(a, vec, tiles, edge, s);
     });
 }
 
@@ -94,16 +97,17 @@ int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs
     if (st != DSK_OK) return st;
     const bool vec = vec_ok(t, d, width, in, in_is_f32, vol);
     const int64_t tiles = tiles_x(width, t, vec);
-    if (tiles * (int64_t)d.rows > kMaxI32) return DSK_ESHAPE;
+    const int64_t edge = edge_blocks(d, width, t, vec);
+    if (tiles * (int64_t)d.rows + edge > kMaxI32) return DSK_ESHAPE;
     hipError_t e;
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
                          width, d.planes, d.rows, d.cols};
-        e = fwd_dispatch<float>(a, t, vec, tiles, stream);
+        e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
                             width, d.planes, d.rows, d.cols};
-        e = fwd_dispatch<uint16_t>(a, t, vec, tiles, stream);
+        e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);
 }

@@ -262,23 +262,48 @@ struct RawWin<float> {
     }
 };
 
-// One vector tile: row r, columns [x0, x0 + 4*BLOCK*G).  Thread t owns the
-// 4-column groups starting at x0 + 4*(t + BLOCK*g).
+// Column layout of output row r for the vector kernel.  The flat volume
+// index of (n, r, x') has the residue (r*W + x') mod 4 in every plane when
+// rows*W is a multiple of 4, so the 4-aligned groups start at column ca and
+// there are ng whole groups, [ca, ca + 4 ng).  The at most 3 columns before
+// and 3 after (none when W is a multiple of 4) are the row's edge columns.
+struct RowGeo {
+    int ca, ng;
+};
+
+__device__ __forceinline__ RowGeo row_geo(int64_t r, int W) {
+    RowGeo g;
+    const int m = (int)((r * (int64_t)W) & 3);
+    g.ca = (4 - m) & 3;
+    g.ng = W > g.ca ? (W - g.ca) / 4 : 0;
+    return g;
+}
+
+// Edge column j (0..5) of a row, or -1.
+__device__ __forceinline__ int edge_col(const RowGeo &g, int W, int j) {
+    if (j < 3) return (j < g.ca && j < W) ? j : -1;
+    const int x = g.ca + 4 * g.ng + (j - 3);
+    return (x < W && x >= g.ca) ? x : -1;
+}
+
+// One vector tile: row r, whole groups [tile*BLOCK*G, (tile+1)*BLOCK*G) of
+// the row.  Thread t owns groups tile*BLOCK*G + t + BLOCK*g, clamped to the
+// row's last group, so every lane writes whole 16-byte groups (lanes past
+// the end repeat the last group: identical values to identical addresses).
 //
 // Planes are handled in chunks of 64.  For a chunk, lane l of every
-// wavefront computes plane (c0 + l)'s coefficients, its window offset and,
-// per group, whether the wavefront's 256 columns read entirely inside the
-// raw row (IN), entirely outside it (OUT: padding) or across an end (EDGE).
-// A chunk whose planes are all IN (or all OUT) for a group runs a tight loop
-// with no per-plane classification; the per-plane values come from the
-// chunk lanes by readlane.  The scalar unit is shared by all wavefronts of
-// a compute unit, so per-plane uniform work is kept to a few instructions.
+// wavefront computes plane (c0 + l)'s coefficients and window offset, and
+// the wavefront classifies each of its groups: all planes read inside the
+// raw row (IN), all outside it (OUT: padding), or otherwise (MIXED).  IN and
+// MIXED chunks run a software-pipelined loop (MIXED with clamped loads and
+// masks); OUT chunks only store zeros.  The per-plane values come from the
+// chunk lanes by readlane, so the scalar unit -- shared by all wavefronts of
+// a compute unit -- does a handful of instructions per plane.
 template <typename TIn, int BLOCK, int G, int UNR, bool NT>
 struct VecTile {
-    static constexpr int T = 4 * BLOCK * G;
-    enum { OUT = 0, IN = 1, EDGE = 2 };
+    enum { OUT = 0, IN = 1, MIXED = 2 };
     const FwdArgs<TIn> &a;
-    int r, W, C, N, x0, wv, gmod, lane, lane4;
+    int r, W, C, N, ca, ng, wv, lane, gmod;
     // source window offsets (from the row start, in elements) that keep a
     // 4-aligned 8-element window inside the stack, away from its two ends
     int lo_off, hi_off;
@@ -286,21 +311,26 @@ struct VecTile {
     int64_t rstep, ostep, total;
     const TIn *rp0;                    // row r of plane 0
     float *op0;                        // volume row r of plane 0 (or null)
-    bool full[G], wfull[G];
+    int gi[G], gfirst[G], glast[G];
+    bool alive;
     double acc[G][4];
     float mx[G][4];
     // chunk lane data (plane c0 + lane)
     int ls0, lobsh;                    // window start s0, and (s0 - sh) * 4 + sh
     float lwlo, lwhi;
 
-    __device__ __forceinline__ VecTile(const FwdArgs<TIn> &args, int row, int x0_)
-        : a(args), r(row), W((int)args.W), C(args.C), N(args.N), x0(x0_) {
+    __device__ __forceinline__ VecTile(const FwdArgs<TIn> &args, int row, int tile)
+        : a(args), r(row), W((int)args.W), C(args.C), N(args.N) {
+        const RowGeo rg = row_geo(r, W);
+        ca = rg.ca;
+        ng = rg.ng;
         total = (int64_t)N * a.R * C;
         rstep = (int64_t)a.R * C;
         ostep = (int64_t)a.R * W;
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
         lane = (int)threadIdx.x & 63;
-        lane4 = 4 * lane;
+        const int base = tile * BLOCK * G;
+        alive = base + 64 * wv < ng;
         // rows*C is a multiple of 4, so every plane's row start has this residue
         gmod = (int)(((int64_t)r * C) & 3);
         lo_off = -8 + ((-gmod) & 3);
@@ -313,10 +343,10 @@ struct VecTile {
         op0 = a.vol ? a.vol + (int64_t)r * W : nullptr;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int xg = x0 + 4 * ((int)threadIdx.x + BLOCK * g);
-            full[g] = xg >= 0 && xg + 4 <= W;
-            const int w0 = x0 + cg(g);
-            wfull[g] = w0 >= 0 && w0 + 256 <= W;
+            const int w0 = base + 64 * wv + BLOCK * g;
+            gi[g] = min(base + (int)threadIdx.x + BLOCK * g, ng - 1);
+            gfirst[g] = min(w0, ng - 1);
+            glast[g] = min(w0 + 63, ng - 1);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 acc[g][i] = 0.0;
@@ -325,16 +355,15 @@ struct VecTile {
         }
     }
 
-    __device__ __forceinline__ int cg(int g) const { return 4 * (64 * wv + BLOCK * g); }
-    __device__ __forceinline__ int xg(int g) const { return x0 + 4 * ((int)threadIdx.x + BLOCK * g); }
+    __device__ __forceinline__ int xcol(int g) const { return ca + 4 * gi[g]; }
 
-    // Class of the wavefront's group g for window start s0: its positions are
-    // [s0 + cg, s0 + cg + 257).
+    // Positions [s0 + 4 gfirst, s0 + 4 glast + 5) of the wavefront's group g.
     __device__ __forceinline__ int cls_of(int s0, int g) const {
-        const int q = s0 + cg(g);
-        if (q >= 0 && q + 257 <= C) return IN;
-        if (q + 257 <= 0 || q >= C) return OUT;
-        return EDGE;
+        const int q0 = s0 + 4 * gfirst[g];
+        const int q1 = s0 + 4 * glast[g] + 5;
+        if (q0 >= 0 && q1 <= C) return IN;
+        if (q1 <= 0 || q0 >= C) return OUT;
+        return MIXED;
     }
 
     __device__ __forceinline__ void chunk(int c0) {
@@ -348,28 +377,15 @@ struct VecTile {
             o = __dmul_rn((double)n, a.shift);
         }
         const PlaneCoef pc = coef_from_offset(o, a.origin);
-        // window start; beyond +-2^28 every position lies outside the row
-        // (rows and widths of this kernel are below 2^27), so clamp there
-        const int s0l = x0 - pc.k - 1;
+        // window start of group 0; beyond +-2^28 every position lies outside
+        // the row (rows and widths of this kernel are below 2^27): clamp there
+        const int s0l = ca - pc.k - 1;
         const int s0 = s0l < -(1 << 28) ? -(1 << 28) : (s0l > (1 << 28) ? (1 << 28) : s0l);
         const int sh = (gmod + s0) & 3;
         ls0 = s0;
         lobsh = (s0 - sh) * 4 + sh;
         lwlo = pc.wlo;
         lwhi = pc.whi;
-    }
-
-    __device__ __forceinline__ void store(float *orow, int g, const float d[4]) const {
-        float *o = orow + xg(g);
-        if (wfull[g]) {                  // uniform: the whole wavefront is inside the row
-            store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
-        } else if (full[g]) {
-            store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
-        } else {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (xg(g) + i >= 0 && xg(g) + i < W) store_f32<NT>(o + i, d[i]);
-        }
     }
 
     __device__ __forceinline__ void interp(int g, const float v[5], float wlo, float whi,
@@ -382,49 +398,62 @@ struct VecTile {
         }
     }
 
-    // Issue the loads of chunk planes [li0, li0 + U) for group g (indices
-    // past the chunk end repeat its last plane: in bounds, never used).
-    template <int U>
+    // Loads of chunk planes [li0, li0 + U) for group g (indices past the
+    // chunk end repeat its last plane: in bounds, never used).  MASK clamps
+    // the window into the row's neighbourhood (lanes reaching outside the
+    // row only read values that are masked afterwards).
+    template <int U, bool MASK>
     __device__ __forceinline__ void issue(int g, int li0, int cn, const TIn *rpc,
                                           RawWin<TIn> raw[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int li = min(li0 + u, cn - 1);
             const int v = __builtin_amdgcn_readlane(lobsh, li);
-            raw[u].load(rpc + (int64_t)li * rstep, (v >> 2) + cg(g) + lane4, v & 3);
+            int off = (v >> 2) + 4 * gi[g];
+            if (MASK) off = off < lo_off ? lo_off : (off > hi_off ? hi_off : off);
+            raw[u].load(rpc + (int64_t)li * rstep, off, v & 3);
         }
     }
 
-    // Chunk planes [0, cn) all inside the row for group g, with every
-    // column of this wavefront inside the frame (wfull), software-pipelined:
-    // the loads of the next U planes go out before the current U planes are
-    // interpolated and stored, and are waited for after those stores.  Each
-    // plane issues exactly one 16-byte store per lane (no branch around it),
-    // so the compiler can count the stores and the wait for the loads leaves
-    // them in flight: stores never hold up the plane loop.
-    template <int U, bool VOL>
-    __device__ __forceinline__ void in_loop(int g, int cn, const TIn *rpc, float *op) {
+    template <bool MASK>
+    __device__ __forceinline__ void compute(int g, const RawWin<TIn> &raw, int li, float d[4]) {
+        const int v = __builtin_amdgcn_readlane(lobsh, li);
+        const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
+        const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
+        const int sh = v & 3;
+        float vv[5];
+        raw.extract(sh, vv);
+        if (MASK) {
+            const int p = (v >> 2) + sh + 4 * gi[g];
+#pragma unroll
+            for (int i = 0; i < 5; ++i)
+                if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
+        }
+        interp(g, vv, wlo, whi, d);
+    }
+
+    // Chunk planes [0, cn) for group g, software-pipelined: the loads of the
+    // next U planes go out before the current U planes are interpolated and
+    // stored, and are waited for after those stores.  Each plane issues
+    // exactly one 16-byte store per lane with no branch around it, so the
+    // compiler counts the stores and the wait for the loads leaves them in
+    // flight: stores never hold up the plane loop.
+    template <int U, bool MASK, bool VOL>
+    __device__ __forceinline__ void pipe_loop(int g, int cn, const TIn *rpc, float *op) {
         const int groups = cn / U;
-        float *o = VOL ? op + xg(g) : nullptr;
+        float *o = VOL ? op + xcol(g) : nullptr;
         if (groups > 0) {
             RawWin<TIn> cur[U];
-            issue<U>(g, 0, cn, rpc, cur);
+            issue<U, MASK>(g, 0, cn, rpc, cur);
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u].settle();
-            for (int gi = 0; gi < groups; ++gi) {
+            for (int k = 0; k < groups; ++k) {
                 RawWin<TIn> nxt[U];
-                issue<U>(g, (gi + 1) * U, cn, rpc, nxt);
+                issue<U, MASK>(g, (k + 1) * U, cn, rpc, nxt);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int li = gi * U + u;
-                    const int v = __builtin_amdgcn_readlane(lobsh, li);
-                    const float wlo =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
-                    const float whi =
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
-                    float vv[5], d[4];
-                    cur[u].extract(v & 3, vv);
-                    interp(g, vv, wlo, whi, d);
+                    float d[4];
+                    compute<MASK>(g, cur[u], k * U + u, d);
                     if constexpr (VOL) {
                         store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
                         o += ostep;
@@ -439,13 +468,9 @@ struct VecTile {
         }
         for (int li = groups * U; li < cn; ++li) {
             RawWin<TIn> one[1];
-            issue<1>(g, li, cn, rpc, one);
-            const int v = __builtin_amdgcn_readlane(lobsh, li);
-            const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
-            const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
-            float vv[5], d[4];
-            one[0].extract(v & 3, vv);
-            interp(g, vv, wlo, whi, d);
+            issue<1, MASK>(g, li, cn, rpc, one);
+            float d[4];
+            compute<MASK>(g, one[0], li, d);
             if constexpr (VOL) {
                 store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
                 o += ostep;
@@ -453,122 +478,157 @@ struct VecTile {
         }
     }
 
-    // One plane in general position for group g (chunk lane li, plane n).
-    __device__ __forceinline__ void step_edge(int g, int li, int n, const TIn *rp, float *op) {
-        const int s0 = __builtin_amdgcn_readlane(ls0, li);
-        const int v = __builtin_amdgcn_readlane(lobsh, li);
-        const int sh = v & 3;
-        const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
-        const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
-        const int cls = cls_of(s0, g);
-        float d[4];
-        if (cls == OUT) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                d[i] = 0.0f;
-                mx[g][i] = fmaxf(mx[g][i], 0.0f);
+    // Chunk planes whose rows lie at a stack end: windows clamped to the
+    // exact stack bounds; lanes whose window moved reload per pixel.
+    __device__ __forceinline__ void slow_loop(int g, int c0, int cn, const TIn *rpc, float *op) {
+        for (int li = 0; li < cn; ++li) {
+            const int n = c0 + li;
+            const TIn *rp = rpc + (int64_t)li * rstep;
+            const int v = __builtin_amdgcn_readlane(lobsh, li);
+            const int sh = v & 3;
+            const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
+            const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
+            const int p = (v >> 2) + sh + 4 * gi[g];
+            int lo = lo_off, hi = hi_off;
+            if (n == first_special || n == last_special) {
+                const int64_t grow = rp - a.in;
+                lo = (int)(-grow > (int64_t)lo ? -grow : (int64_t)lo);
+                hi = (int)(total - 8 - grow < (int64_t)hi ? total - 8 - grow : (int64_t)hi);
             }
-        } else {
-            const int p = s0 + cg(g) + lane4;
+            const int off = p - sh;
+            const int oc = off < lo ? lo : (off > hi ? hi : off);
             RawWin<TIn> raw;
-            bool moved = false;
-            if (cls == IN) {
-                raw.load(rp, p - sh, sh);
-            } else {
-                int lo = lo_off, hi = hi_off;
-                const bool special = n == first_special || n == last_special;
-                if (special) {
-                    const int64_t grow = rp - a.in;
-                    lo = (int)(-grow > (int64_t)lo ? -grow : (int64_t)lo);
-                    hi = (int)(total - 8 - grow < (int64_t)hi ? total - 8 - grow : (int64_t)hi);
-                }
-                const int off = p - sh;
-                const int oc = off < lo ? lo : (off > hi ? hi : off);
-                moved = special && oc != off;
-                raw.load(rp, oc, sh);
-            }
-            float vv[5];
+            raw.load(rp, oc, sh);
+            float vv[5], d[4];
             raw.extract(sh, vv);
-            if (cls == EDGE) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i)
-                    if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
-                if (moved) {
+            for (int i = 0; i < 5; ++i)
+                if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
+            if (oc != off) {
 #pragma unroll
-                    for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
-                }
+                for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
             }
             interp(g, vv, wlo, whi, d);
+            if (op) store_f32x4<NT>(op + (int64_t)li * ostep + xcol(g), f32x4{d[0], d[1], d[2], d[3]});
         }
-        if (op) store(op, g, d);
     }
 
     __device__ __forceinline__ void run() {
+        if (!alive) return;
         for (int c0 = 0; c0 < N; c0 += 64) {
             const int cn = min(64, N - c0);
             chunk(c0);
             const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < cn);
+            const bool special = (first_special >= c0 && first_special < c0 + cn) ||
+                                 (last_special >= c0 && last_special < c0 + cn);
+            const TIn *rp = rp0 + (int64_t)c0 * rstep;
+            float *op = op0 ? op0 + (int64_t)c0 * ostep : nullptr;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int cl = cls_of(ls0, g);
                 const uint64_t bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
                 const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
-                const TIn *rp = rp0 + (int64_t)c0 * rstep;
-                float *op = op0 ? op0 + (int64_t)c0 * ostep : nullptr;
-                if (bin == valid && wfull[g]) {
-                    if (op)
-                        in_loop<UNR, true>(g, cn, rp, op);
-                    else
-                        in_loop<UNR, false>(g, cn, rp, op);
+                if (special) {
+                    slow_loop(g, c0, cn, rp, op);
                 } else if (bout == valid) {
+                    // padding: zero output, nothing added to the sum
 #pragma unroll
                     for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
                     if (op) {
-                        const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                        float *o = op + xcol(g);
                         for (int li = 0; li < cn; ++li) {
-                            store(op, g, z);
-                            op += ostep;
+                            store_f32x4<NT>(o, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
+                            o += ostep;
                         }
                     }
+                } else if (bin == valid) {
+                    if (op) pipe_loop<UNR, false, true>(g, cn, rp, op);
+                    else pipe_loop<UNR, false, false>(g, cn, rp, op);
                 } else {
-                    for (int li = 0; li < cn; ++li) {
-                        step_edge(g, li, c0 + li, rp, op);
-                        rp += rstep;
-                        if (op) op += ostep;
-                    }
+                    if (op) pipe_loop<UNR, true, true>(g, cn, rp, op);
+                    else pipe_loop<UNR, true, false>(g, cn, rp, op);
                 }
             }
         }
-        finish();
-    }
-
-    __device__ __forceinline__ void finish() {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int x = xg(g) + i;
-                if (x >= 0 && x < W) {
-                    if (a.psum) a.psum[(int64_t)r * W + x] = (float)acc[g][i];
-                    if (a.pmax) a.pmax[(int64_t)r * W + x] = mx[g][i];
-                }
+                const int64_t o = (int64_t)r * W + xcol(g) + i;
+                if (a.psum) a.psum[o] = (float)acc[g][i];
+                if (a.pmax) a.pmax[o] = mx[g][i];
             }
         }
     }
 };
 
-template <typename TIn, int BLOCK, int G, int UNR, bool NT>
-__device__ __forceinline__ void fwd_tile_vec(const FwdArgs<TIn> &a, int r, int tile) {
-    constexpr int T = 4 * BLOCK * G;
-    const int m = (int)(((int64_t)r * a.W) & 3);
-    const int ca = (4 - m) & 3;
-    const int x0 = (ca ? ca - 4 : 0) + tile * T;
-    if (x0 >= a.W) return;
-    VecTile<TIn, BLOCK, G, UNR, NT> vt(a, r, x0);
-    vt.run();
+// Edge columns (the at most 3 unaligned columns at each end of every row,
+// present only when W is not a multiple of 4, and then at least one per
+// row): lane e handles slot e % 6 of row e / 6; empty slots and rows past
+// the end repeat their row's first edge column (identical values to
+// identical addresses), so every lane stays active -- the per-plane
+// coefficients are shared across lanes -- and every store is unconditional.
+// Two pixel loads per plane, issued UNR planes ahead of the stores.  Same
+// per-voxel arithmetic and plane order as every other path.
+template <typename TIn, int UNR, bool NT>
+__device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
+    const int W = (int)a.W, C = a.C;
+    const int r = min(e / 6, a.R - 1);
+    const RowGeo rg = row_geo(r, W);
+    int x = edge_col(rg, W, e - 6 * (e / 6));
+    for (int j = 0; j < 6 && x < 0; ++j) x = edge_col(rg, W, j);
+    if (x < 0) x = 0;   // unreachable when W % 4 != 0
+    const int64_t rstep = (int64_t)a.R * C, ostep = (int64_t)a.R * W;
+    const TIn *rp = a.in + (int64_t)r * C;
+    float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
+    CoefCache cc;
+    cc.init(a.offs, a.shift, a.origin, a.N);
+    double acc = 0.0;
+    float mx = -__builtin_huge_valf();
+    float lo[UNR], hi[UNR], wlo[UNR], whi[UNR];
+    auto issue = [&](int n0, float l[UNR], float h[UNR], float wl[UNR], float wh[UNR]) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int n = min(n0 + u, a.N - 1);
+            const PlaneCoef pc = cc.get(n);
+            const int64_t i = (int64_t)x - pc.k;
+            const TIn *row = rp + (int64_t)n * rstep;
+            h[u] = load_px(row, i, (int64_t)C);
+            l[u] = load_px(row, i - 1, (int64_t)C);
+            wl[u] = pc.wlo;
+            wh[u] = pc.whi;
+        }
+    };
+    issue(0, lo, hi, wlo, whi);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) asm volatile("" ::"v"(lo[u]), "v"(hi[u]));
+    for (int n0 = 0; n0 < a.N; n0 += UNR) {
+        float lo2[UNR], hi2[UNR], wlo2[UNR], whi2[UNR];
+        issue(n0 + UNR, lo2, hi2, wlo2, whi2);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (n0 + u < a.N) {
+                const float d = fmaf(whi[u], hi[u], wlo[u] * lo[u]);
+                acc += (double)d;
+                mx = fmaxf(mx, d);
+                if (op) store_f32<NT>(op + (int64_t)(n0 + u) * ostep, d);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            asm volatile("" ::"v"(lo2[u]), "v"(hi2[u]));
+            lo[u] = lo2[u];
+            hi[u] = hi2[u];
+            wlo[u] = wlo2[u];
+            whi[u] = whi2[u];
+        }
+    }
+    if (a.psum) a.psum[(int64_t)r * W + x] = (float)acc;
+    if (a.pmax) a.pmax[(int64_t)r * W + x] = mx;
 }
 
-// Plain launches: one workgroup per (row, column tile).
+// Plain launches: one workgroup per (row, tile); vector launches add
+// `edge_blocks` workgroups for the edge columns.
 template <typename TIn, int BLOCK, int J, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_forward_scalar(FwdArgs<TIn> a, int tiles_x) {
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
@@ -578,11 +638,21 @@ __global__ __launch_bounds__(BLOCK) void k_forward_scalar(FwdArgs<TIn> a, int ti
 }
 
 template <typename TIn, int BLOCK, int G, int UNR, bool NT>
+__device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x, int64_t b) {
+    const int64_t main = (int64_t)a.R * tiles_x;
+    if (b < main) {
+        const int r = (int)(b / tiles_x);
+        const int xt = (int)(b - (int64_t)r * tiles_x);
+        VecTile<TIn, BLOCK, G, UNR, NT> vt(a, r, xt);
+        vt.run();
+    } else {
+        fwd_edge_lane<TIn, UNR, NT>(a, (int)((b - main) * BLOCK + threadIdx.x));
+    }
+}
+
+template <typename TIn, int BLOCK, int G, int UNR, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_forward_vec(FwdArgs<TIn> a, int tiles_x) {
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    const int r = (int)(b / tiles_x);
-    const int xt = (int)(b - (int64_t)r * tiles_x);
-    fwd_tile_vec<TIn, BLOCK, G, UNR, NT>(a, r, xt);
+    fwd_vec_block<TIn, BLOCK, G, UNR, NT>(a, tiles_x, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // Job record of the persistent ragged-batch kernel (device-resident table).
@@ -594,12 +664,12 @@ struct JobDev {
     int64_t W;
     int64_t tile_begin;  // first global tile index of this job
     int32_t N, R, C, tiles_x;
-    int32_t vec, pad_;
+    int32_t vec, edge_blocks;
 };
 
 // Persistent launch: workgroups stride over the concatenated tile lists of
-// all jobs (job-major, then row, then column tile).  Each tile runs exactly
-// the code of the plain launch for that job, so outputs are bitwise equal.
+// all jobs (job-major).  Each tile runs exactly the code of the plain launch
+// for that job, so outputs are bitwise equal.
 template <int BLOCK, int PT, int UNR, bool NT>
 __global__ __launch_bounds__(BLOCK) void k_forward_jobs(const JobDev *__restrict__ jobs,
                                                         int n_jobs, int64_t total_tiles) {
@@ -629,14 +699,14 @@ __global__ __launch_bounds__(BLOCK) void k_forward_jobs(const JobDev *__restrict
         a.R = jb.R;
         a.C = jb.C;
         const int64_t lt = t - jb.tile_begin;
-        const int r = (int)(lt / jb.tiles_x);
-        const int xt = (int)(lt - (int64_t)r * jb.tiles_x);
         if constexpr (PT >= 4) {
             if (jb.vec) {
-                fwd_tile_vec<uint16_t, BLOCK, PT / 4, UNR, NT>(a, r, xt);
+                fwd_vec_block<uint16_t, BLOCK, PT / 4, UNR, NT>(a, jb.tiles_x, lt);
                 continue;
             }
         }
+        const int r = (int)(lt / jb.tiles_x);
+        const int xt = (int)(lt - (int64_t)r * jb.tiles_x);
         fwd_tile_scalar<uint16_t, BLOCK, PT, NT>(a, r, (int64_t)xt * (BLOCK * PT));
     }
 }
