@@ -13,6 +13,9 @@ Every function here follows the paper's definitions, cited per function:
                       projection (Fig. 2d) and the sum projection.
   * ``adjoint``    -- transpose of the remap, as an explicit scatter.
   * ``shear_grad`` -- derivative of a loss with respect to each image offset.
+  * ``view_geometry``, ``warp``, ``view`` -- the shear-warp rotated view
+                      (Fig. 3): projection of the stack remapped with a
+                      changed shift, stretched along the column axis.
 """
 import ctypes
 import os
@@ -55,6 +58,12 @@ def _load():
     lib.orc_shear_grad.restype = None
     lib.orc_shear_grad.argtypes = [_fp, _fp, _i64, _i64, _i64, _dp, _i64,
                                    _i64, _dp]
+    lib.orc_view_geometry.restype = None
+    lib.orc_view_geometry.argtypes = [ctypes.c_double] * 4 + [_dp, _dp]
+    lib.orc_view_width.restype = _i64
+    lib.orc_view_width.argtypes = [_i64, ctypes.c_double]
+    lib.orc_warp.restype = None
+    lib.orc_warp.argtypes = [_dp, _i64, _i64, ctypes.c_double, _i64, _dp]
     _lib = lib
     return lib
 
@@ -158,3 +167,48 @@ def shear_grad(stack, grad_vol, offsets, origin):
     _load().orc_shear_grad(_ptr(s, _fp), _ptr(g, _fp), n, r, c, _ptr(o, _dp),
                            int(origin), w, _ptr(out, _dp))
     return out
+
+
+def view_geometry(theta_deg, angle_deg, step_um, pixel_um):
+    """(shift per image s', stretch factor) of the view at ``theta_deg`` from
+    the optical axis: s' = z cos(theta) / (p cos(theta - alpha)), stretch
+    cos(theta - alpha) (Fig. 3)."""
+    s, w = ctypes.c_double(), ctypes.c_double()
+    _load().orc_view_geometry(float(theta_deg), float(angle_deg), float(step_um),
+                              float(pixel_um), ctypes.byref(s), ctypes.byref(w))
+    return s.value, w.value
+
+
+def view_width(width_in, warp_factor):
+    """View columns whose source coordinate j / warp lies in the projection."""
+    return int(_load().orc_view_width(int(width_in), float(warp_factor)))
+
+
+def warp(proj, warp_factor, width_out=None):
+    """Stretch every row of ``proj`` [R][W] along the column axis: view
+    column j is the linear interpolation of the row at j / warp (zero
+    outside).  FP64 in and out."""
+    p = np.ascontiguousarray(proj, np.float64)
+    rows, w_in = p.shape
+    if width_out is None:
+        width_out = view_width(w_in, warp_factor)
+    out = np.empty((rows, width_out), np.float64)
+    _load().orc_warp(_ptr(p, _dp), rows, w_in, float(warp_factor), int(width_out),
+                     _ptr(out, _dp))
+    return out
+
+
+def view(stack, theta_deg, angle_deg, step_um, pixel_um, width_out=None):
+    """Shear-warp view (Fig. 3): remap with the view's shift s', project over
+    the image axis, stretch the projections by the view's factor.  Returns a
+    dict with ``psum``/``pmax`` (FP64 [R][width_out]) and the geometry."""
+    n, r, c = np.shape(stack)
+    s, wf = view_geometry(theta_deg, angle_deg, step_um, pixel_um)
+    offs = offsets_uniform(n, s)
+    b, w_in = frame(offs, c)
+    d = deskew(stack, offs, b, w_in, vol=False)
+    if width_out is None:
+        width_out = view_width(w_in, wf)
+    return {"shear": s, "warp": wf, "origin": b, "proj_width": w_in,
+            "width": int(width_out),
+            "psum": warp(d["psum"], wf, width_out), "pmax": warp(d["pmax"], wf, width_out)}

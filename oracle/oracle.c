@@ -196,3 +196,59 @@ void orc_shear_grad(const float *stack, const float *grad_vol,
         grad_off[n] = acc;
     }
 }
+
+/* Shear-warp rotated view (Fig. 3 and the shear-warp paragraph of
+ * "Physical principles"): remapping with a different shift per image and
+ * then stretching the projection along the column axis renders the
+ * projection of the sample seen from another direction.
+ *
+ * Geometry, in the plane spanned by the scan axis (coordinate Y) and the
+ * optical axis (height Z): a point (Y, Z) is recorded in image
+ * n = (Y - Z cot(alpha)) / z at raw column c = Z / (p sin(alpha)).  Remapped
+ * with a shift of s' pixels per image it lands at
+ *     x' = c + n s' - b = Y s' / z + Z (1 / (p sin(alpha)) - s' cot(alpha) / z) - b.
+ * Projecting along the image axis collapses every point with the same x',
+ * so the projection is the view along the direction in which x' is
+ * constant.  Its image coordinate for a view that makes angle theta with
+ * the optical axis is u = Y cos(theta) + Z sin(theta); x' is proportional
+ * to u exactly when
+ *     s' = z cos(theta) / (p cos(theta - alpha)),
+ * and then x' + b = u / (p cos(theta - alpha)): the warp that turns x' into
+ * view pixels u / p is a stretch by cos(theta - alpha).  theta = alpha gives
+ * back Eq. 1 with no stretch; theta = 0 looks down the optical axis. */
+void orc_view_geometry(double theta_deg, double angle_deg, double step_um,
+                       double pixel_um, double *shear_px, double *warp)
+{
+    double theta = theta_deg * ORC_PI / 180.0;
+    double alpha = angle_deg * ORC_PI / 180.0;
+    *shear_px = step_um * cos(theta) / (pixel_um * cos(theta - alpha));
+    *warp = cos(theta - alpha);
+}
+
+/* Number of view columns j = 0, 1, ... whose source coordinate j / warp
+ * stays inside the projection's width_in columns. */
+int64_t orc_view_width(int64_t width_in, double warp)
+{
+    return (int64_t)floor((double)(width_in - 1) * warp) + 1;
+}
+
+/* The warp: view column j samples the projection row at x' = j / warp with
+ * linear interpolation, zero outside [0, width_in).  proj is
+ * [rows][width_in], out is [rows][width_out], both FP64. */
+void orc_warp(const double *proj, int64_t rows, int64_t width_in,
+              double warp, int64_t width_out, double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t r = 0; r < rows; ++r) {
+        const double *p = proj + (size_t)(r * width_in);
+        for (int64_t j = 0; j < width_out; ++j) {
+            double u = (double)j / warp;
+            double fi = floor(u);
+            double f = u - fi;
+            int64_t i = (int64_t)fi;
+            double a = (i >= 0 && i < width_in) ? p[i] : 0.0;
+            double c = (i + 1 >= 0 && i + 1 < width_in) ? p[i + 1] : 0.0;
+            out[(size_t)(r * width_out + j)] = (1.0 - f) * a + f * c;
+        }
+    }
+}
