@@ -239,6 +239,50 @@ int dsk_rolling_update_u16(const uint16_t *plane, int32_t n, dsk_dims d,
                            float *tree, double *sum64, float *psum,
                            float *pmax, hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Shear-warp rotated view (Fig. 3; shear-warp paragraph of "Physical
+ * principles"): remapping with a changed per-image shift s' and stretching
+ * the projection along the column axis renders the projection seen from
+ * another direction.  For a view at angle theta to the optical axis, in the
+ * plane of the scan axis and the optical axis (theta = alpha is the plain
+ * deskew, theta = 0 looks straight down the optical axis):
+ *     s'      = z cos(theta) / (p cos(theta - alpha))   pixels per image
+ *     stretch = cos(theta - alpha)
+ * A point at scan position Y and height Z lands in view column
+ * (Y cos(theta) + Z sin(theta)) / p - stretch * b.  Requires
+ * |theta - alpha| < 90 degrees.
+ * ------------------------------------------------------------------- */
+
+/* Host-only geometry of the view: shift per image, stretch, the remap frame
+ * (proj_width, origin) of the shifted images and the view width
+ * floor((proj_width - 1) * stretch) + 1.  Any output pointer may be NULL. */
+int dsk_view_plan(dsk_dims d, dsk_geom g, double theta_deg, double *shear_px,
+                  double *stretch, int64_t *proj_width, int64_t *origin,
+                  int64_t *view_width);
+
+/* Workspace bytes dsk_view_u16 needs: the two [rows][proj_width] float32
+ * projections of the shifted images. */
+size_t dsk_view_workspace_bytes(dsk_dims d, int64_t proj_width);
+
+/* The view of a uint16 stack: projections of the stack remapped with
+ * offsets n * shear_px in the frame (origin, proj_width), then stretched:
+ * view column j samples the projection row at x' = j / stretch by linear
+ * interpolation, zero outside [0, proj_width).  vsum / vmax are
+ * [rows][view_width] float32 (either may be NULL, not both).  workspace:
+ * DEVICE, 16-byte aligned, at least dsk_view_workspace_bytes bytes, owned
+ * by the caller and overwritten. */
+int dsk_view_u16(const uint16_t *in, dsk_dims d, double shear_px,
+                 double stretch, int64_t origin, int64_t proj_width,
+                 float *vsum, float *vmax, int64_t view_width,
+                 void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* The stretch alone: out[r][j] = linear interpolation of proj[r][.] at
+ * j / stretch (zero outside [0, width_in)); proj [rows][width_in], out
+ * [rows][width_out], both DEVICE float32. */
+int dsk_stretch_f32(const float *proj, int64_t rows, int64_t width_in,
+                    double stretch, float *out, int64_t width_out,
+                    hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,10 +2,13 @@
 
 The hot path -- remap of every raw image to its lateral offset (Eq. 1) with
 fused sum and maximum projections, its adjoint and shear gradient, ragged
-batches and the live serving loop -- runs in the HIP kernels of
+batches, the live serving loop, the rolling update and shear-warp rotated
+views -- runs in the HIP kernels of
 ``libdeskew.so`` (C ABI in ``include/deskew.h``).  Import is light: the
 library is loaded on first use and its absence is an error, never a fallback.
 """
-from .api import adjoint, backward, deskew, plan, shear_grad, shift_px  # noqa: F401
+from .api import (adjoint, backward, deskew, plan, shear_grad, shift_px, stretch,  # noqa: F401
+                  view, view_plan)
 
-__all__ = ["deskew", "plan", "shift_px", "backward", "adjoint", "shear_grad"]
+__all__ = ["deskew", "plan", "shift_px", "backward", "adjoint", "shear_grad", "view",
+           "view_plan", "stretch"]

@@ -76,6 +76,13 @@ _SIGS = {
                                               c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "dsk_jobs_launch": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int, c_vp, c_vp, c_sz,
                                        ctypes.POINTER(Tune), c_vp]),
+    "dsk_view_plan": (ctypes.c_int, [Dims, Geom, c_dbl, ctypes.POINTER(c_dbl),
+                                     ctypes.POINTER(c_dbl), ctypes.POINTER(c_i64),
+                                     ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
+    "dsk_view_workspace_bytes": (c_sz, [Dims, c_i64]),
+    "dsk_view_u16": (ctypes.c_int, [c_vp, Dims, c_dbl, c_dbl, c_i64, c_i64, c_vp, c_vp, c_i64,
+                                    c_vp, c_sz, c_vp]),
+    "dsk_stretch_f32": (ctypes.c_int, [c_vp, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp]),
 }
 
 _lib = None

@@ -208,3 +208,63 @@ def shear_grad(stack, grad_vol, offsets_dev, origin, stream=None):
                                 int(origin), int(w), _vp(go), _vp(ws), wsb, _stream(stream))
     L.check(st, "dsk_shear_grad_f32")
     return go
+
+
+def view_plan(shape, theta_deg, angle_deg, step_um, pixel_um):
+    """Geometry of the shear-warp view at ``theta_deg`` from the optical axis
+    (Fig. 3): dict with the per-image ``shear`` s' = z cos(theta) /
+    (p cos(theta - alpha)), the column ``stretch`` cos(theta - alpha), the
+    remap frame ``proj_width``/``origin`` and the view ``width``."""
+    s, k = ctypes.c_double(), ctypes.c_double()
+    w, b, vw = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = L.lib().dsk_view_plan(_dims(shape), L.Geom(angle_deg, step_um, pixel_um),
+                               float(theta_deg), ctypes.byref(s), ctypes.byref(k),
+                               ctypes.byref(w), ctypes.byref(b), ctypes.byref(vw))
+    L.check(st, "dsk_view_plan")
+    return {"shear": s.value, "stretch": k.value, "proj_width": int(w.value),
+            "origin": int(b.value), "width": int(vw.value)}
+
+
+def view(stack, theta_deg, angle_deg, step_um, pixel_um, *, vsum=True, vmax=True,
+         width=None, workspace=None, stream=None):
+    """Shear-warp view of a uint16 stack (Fig. 3): remap with the view's
+    shift, project (sum and max) and stretch the projections along the
+    column axis.  Returns a dict with ``vsum``/``vmax`` float32 [rows][width]
+    and the geometry of :func:`view_plan`."""
+    _check_stack(stack, (torch.uint16,))
+    shape = tuple(stack.shape)
+    g = view_plan(shape, theta_deg, angle_deg, step_um, pixel_um)
+    if width is not None:
+        g["width"] = int(width)
+    dims = _dims(shape)
+    lib = L.lib()
+    need = int(lib.dsk_view_workspace_bytes(dims, g["proj_width"]))
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty((max(1, need // 4),), dtype=torch.float32, device=stack.device)
+    r = shape[1]
+    res = dict(g)
+    for key, want in (("vsum", vsum), ("vmax", vmax)):
+        if want:
+            res[key] = torch.empty((r, g["width"]), dtype=torch.float32, device=stack.device)
+    st = lib.dsk_view_u16(_vp(stack), dims, g["shear"], g["stretch"], g["origin"],
+                          g["proj_width"], _vp(res.get("vsum")), _vp(res.get("vmax")),
+                          g["width"], _vp(workspace), need, _stream(stream))
+    L.check(st, "dsk_view_u16")
+    res["_workspace"] = workspace
+    return res
+
+
+def stretch(proj, factor, width=None, stream=None):
+    """Stretch every row of a float32 [rows][W] CUDA tensor along the column
+    axis: column j samples the row at j / factor, linear, zero outside."""
+    if not isinstance(proj, torch.Tensor) or proj.dim() != 2 or not proj.is_cuda or \
+            proj.dtype != torch.float32 or not proj.is_contiguous():
+        raise ValueError("proj must be a contiguous float32 CUDA tensor [rows][W]")
+    rows, w_in = proj.shape
+    if width is None:
+        width = int(np.floor((w_in - 1) * float(factor))) + 1
+    out = torch.empty((rows, int(width)), dtype=torch.float32, device=proj.device)
+    st = L.lib().dsk_stretch_f32(_vp(proj), rows, w_in, float(factor), _vp(out), int(width),
+                                 _stream(stream))
+    L.check(st, "dsk_stretch_f32")
+    return out

@@ -114,3 +114,38 @@ def test_rolling_tree_size():
     f = lambda n: lib.dsk_rolling_tree_bytes(L.Dims(n, 3, 5), 7) // (3 * 7 * 4)
     assert [f(1), f(2), f(3), f(5), f(8), f(512)] == [0, 1, 3, 6, 7, 511]
     assert lib.dsk_rolling_tree_bytes(L.Dims(0, 3, 5), 7) == 0
+
+
+@pytest.mark.parametrize("theta", [-20.0, 0.0, 15.0, 30.0, 60.0, 85.0])
+def test_view_plan_follows_view_geometry(theta):
+    import oracle
+    shape = (64, 8, 256)
+    g = api.view_plan(shape, theta, 30.0, 0.4, 0.115)
+    s, k = oracle.view_geometry(theta, 30.0, 0.4, 0.115)
+    assert g["shear"] == s and g["stretch"] == k
+    b, w = oracle.frame(oracle.offsets_uniform(64, s), 256)
+    assert (g["origin"], g["proj_width"]) == (b, w)
+    assert g["width"] == oracle.view_width(w, k)
+
+
+def test_view_entry_points_reject_bad_arguments_before_any_launch():
+    lib = L.lib()
+    d = L.Dims(4, 2, 8)
+    fake = ctypes.c_void_p(0x1000)
+    out = ctypes.c_double()
+    # a view edge-on to the sheet (|theta - alpha| = 90 degrees) has no stretch
+    assert lib.dsk_view_plan(d, L.Geom(30.0, 0.4, 0.115), 120.0, ctypes.byref(out), None, None,
+                             None, None) == L.DSK_EINVAL
+    assert lib.dsk_view_plan(d, L.Geom(30.0, 0.4, 0.115), float("nan"), None, None, None, None,
+                             None) == L.DSK_EINVAL
+    assert lib.dsk_view_workspace_bytes(d, 20) == 2 * 4 * 2 * 20
+    assert lib.dsk_view_workspace_bytes(L.Dims(0, 2, 8), 20) == 0
+    ws = ctypes.c_void_p(0x10000)
+    assert lib.dsk_view_u16(None, d, 1.0, 0.9, 0, 20, fake, fake, 18, ws, 320, None) == L.DSK_EINVAL
+    assert lib.dsk_view_u16(fake, d, 1.0, 0.9, 0, 20, None, None, 18, ws, 320, None) == L.DSK_EINVAL
+    assert lib.dsk_view_u16(fake, d, 1.0, 0.0, 0, 20, fake, None, 18, ws, 320, None) == L.DSK_EINVAL
+    assert lib.dsk_view_u16(fake, d, 1.0, 0.9, 0, 20, fake, None, 18, ws, 319, None) == L.DSK_ESHAPE
+    assert lib.dsk_view_u16(fake, d, 1.0, 0.9, 0, 20, fake, None, 18, ctypes.c_void_p(0x10004),
+                            320, None) == L.DSK_EINVAL
+    assert lib.dsk_stretch_f32(fake, 2, 20, float("inf"), fake, 18, None) == L.DSK_EINVAL
+    assert lib.dsk_stretch_f32(fake, 2, 20, 0.9, None, 18, None) == L.DSK_EINVAL
