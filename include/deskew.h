@@ -72,9 +72,14 @@ typedef struct {
  * nt_store: 1 streams the volume with non-temporal stores; unroll: planes
  * whose loads are issued together (1, 2 or 4); wg_per_cu: resident
  * workgroups per compute unit for the persistent batch kernel (0 = as many
- * as fit).  Every shape gives bitwise identical results. */
+ * as fit); pace_gbs: plane pacing of the vector kernel -- a wavefront that
+ * runs ahead of the schedule "the launch's resident wavefronts move this
+ * many GB/s" sleeps briefly, which keeps the wavefronts on neighbouring
+ * planes and the write stream local (0 = no pacing; pacing only delays,
+ * it never waits on another wavefront).  Every shape gives bitwise
+ * identical results. */
 typedef struct {
-    int32_t block, per_thread, nt_store, unroll, wg_per_cu;
+    int32_t block, per_thread, nt_store, unroll, wg_per_cu, pace_gbs;
 } dsk_tune;
 
 /* Human-readable name of a dsk_status value (static storage). */

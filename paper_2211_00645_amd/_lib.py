@@ -26,7 +26,7 @@ class Geom(ctypes.Structure):
 
 class Tune(ctypes.Structure):
     _fields_ = [("block", c_i32), ("per_thread", c_i32), ("nt_store", c_i32),
-                ("unroll", c_i32), ("wg_per_cu", c_i32)]
+                ("unroll", c_i32), ("wg_per_cu", c_i32), ("pace_gbs", c_i32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

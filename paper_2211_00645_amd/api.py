@@ -45,9 +45,9 @@ def _tune(t):
         return None
     if isinstance(t, L.Tune):
         return t
-    return L.Tune(int(t.get("block", 256)), int(t.get("per_thread", 4)),
-                  int(t.get("nt_store", 0)), int(t.get("unroll", 2)),
-                  int(t.get("wg_per_cu", 0)))
+    return L.Tune(int(t.get("block", 64)), int(t.get("per_thread", 4)),
+                  int(t.get("nt_store", 1)), int(t.get("unroll", 2)),
+                  int(t.get("wg_per_cu", 0)), int(t.get("pace_gbs", 0)))
 
 
 def shift_px(angle_deg: float, step_um: float, pixel_um: float) -> float:

@@ -72,6 +72,7 @@ int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out)
         r.tiles_x = (int32_t)tx;
         r.vec = vec ? 1 : 0;
         r.edge_blocks = (int32_t)eb;
+        r.tau256 = 0;
         out[i] = r;
         begin += tx * j.dims.rows + eb;
         if (begin < 0 || begin > (int64_t(1) << 50)) return -1;
@@ -94,6 +95,18 @@ int persistent_grid(const dsk_tune &t, int64_t total_tiles) {
     if (g > total_tiles) g = total_tiles;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+// Plane pacing of each job: the grid's resident workgroups sweep a job's
+// tiles together, so the share of the job running at once is grid / tiles.
+void set_pacing(JobDev *tab, int n, const dsk_tune &t, int grid) {
+    for (int i = 0; i < n; ++i) {
+        JobDev &r = tab[i];
+        const double blocks = (double)r.tiles_x * r.R + r.edge_blocks;
+        const double plane_bytes =
+            2.0 * (double)r.R * r.C + (r.vol ? 4.0 * (double)r.R * (double)r.W : 0.0);
+        r.tau256 = r.vec ? pace_tau256(plane_bytes, (double)grid / blocks, t.pace_gbs) : 0u;
+    }
 }
 
 hipError_t launch_jobs(const JobDev *table, int n, int64_t total, int grid, const dsk_tune &t,
@@ -143,9 +156,9 @@ bool cache_lookup(const char *path, const std::string &key, dsk_tune *t, double 
         double m = 0.0;
         if (std::sscanf(line,
                         " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                        "\"unroll\": %d, \"wg_per_cu\": %d, \"ms\": %lf}",
-                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu,
-                        &m) == 7 &&
+                        "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf}",
+                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu, &c.pace_gbs,
+                        &m) == 8 &&
             key == k && tune_ok(c)) {
             *t = c;
             *ms = m;
@@ -174,8 +187,9 @@ void cache_store(const char *path, const std::string &key, const dsk_tune &t, do
     char ent[512];
     std::snprintf(ent, sizeof ent,
                   "  \"%s\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                  "\"unroll\": %d, \"wg_per_cu\": %d, \"ms\": %.6f}",
-                  key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu, ms);
+                  "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %.6f}",
+                  key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu,
+                  t.pace_gbs, ms);
     keep.push_back(ent);
     const std::string tmp = std::string(path) + ".tmp";
     std::FILE *f = std::fopen(tmp.c_str(), "w");
@@ -191,10 +205,10 @@ void cache_store(const char *path, const std::string &key, const dsk_tune &t, do
 // Launch shapes the autotuner times.
 std::vector<dsk_tune> candidates() {
     std::vector<dsk_tune> c;
-    for (int b : {128, 256})
-        for (int j : {4, 8})
-            for (int u : {1, 2})
-                for (int nt : {0, 1}) c.push_back(dsk_tune{b, j, nt, u, 0});
+    for (int b : {64, 128})
+        for (int u : {1, 2, 4})
+            for (int pace : {0, 5000, 5500}) c.push_back(dsk_tune{b, 4, 1, u, 0, pace});
+    c.push_back(dsk_tune{256, 8, 1, 2, 0, 0});
     return c;
 }
 
@@ -202,13 +216,16 @@ int upload_table(dsk_batch *bt, const dsk_tune &t, hipStream_t s) {
     std::vector<JobDev> host((size_t)bt->n_jobs);
     const int64_t total = encode_table(bt->jobs.data(), bt->n_jobs, t, host.data());
     if (total <= 0) return DSK_ESHAPE;
+    const int grid = persistent_grid(t, total);
+    if (grid <= 0) return DSK_EHIP;
+    set_pacing(host.data(), bt->n_jobs, t, grid);
     hipError_t e = hipMemcpyAsync(bt->table_dev, host.data(), host.size() * sizeof(JobDev),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return DSK_EHIP;
     bt->total_tiles = total;
-    bt->grid = persistent_grid(t, total);
-    return bt->grid > 0 ? DSK_OK : DSK_EHIP;
+    bt->grid = grid;
+    return DSK_OK;
 }
 
 // Best of `reps` timed launches (ms) of shape t.
@@ -367,6 +384,7 @@ extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host
     if (total <= 0) return DSK_ESHAPE;
     const int grid = persistent_grid(t, total);
     if (grid <= 0) return DSK_EHIP;
+    set_pacing(host, n_jobs, t, grid);
     hipError_t e = hipMemcpyAsync(table_dev, host, dsk_jobs_table_bytes(n_jobs),
                                   hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = launch_jobs((const JobDev *)table_dev, n_jobs, total, grid, t, stream);

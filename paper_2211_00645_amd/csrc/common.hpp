@@ -13,7 +13,7 @@ namespace dsk {
 constexpr int64_t kMaxI32 = 2147483647;
 
 // Default forward launch shape.
-constexpr dsk_tune kDefaultTune = {256, 4, 0, 2, 0};
+constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5500};
 
 inline bool dims_ok(dsk_dims d) {
     return d.planes > 0 && d.rows > 0 && d.cols > 0;
@@ -25,8 +25,22 @@ inline bool tune_ok(const dsk_tune &t) {
                    t.per_thread == 8;
     const bool u = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
     return b && j && u && (t.nt_store == 0 || t.nt_store == 1) && t.wg_per_cu >= 0 &&
-           t.wg_per_cu <= 64;
+           t.wg_per_cu <= 64 && t.pace_gbs >= 0 && t.pace_gbs <= 1000000;
 }
+
+// Plane pacing period in 1/256 ticks of the 100 MHz real-time clock: the
+// time the resident wavefronts take to move one plane's bytes at pace_gbs.
+// plane_bytes is one plane's traffic of the whole launch, resident the
+// fraction of its wavefronts that run at once.  0 = no pacing.
+inline uint32_t pace_tau256(double plane_bytes, double resident, int pace_gbs) {
+    if (pace_gbs <= 0 || !(plane_bytes > 0.0)) return 0;
+    const double r = resident > 1.0 ? 1.0 : (resident > 0.0 ? resident : 1.0);
+    const double t = plane_bytes * r / ((double)pace_gbs * 1e9) * 1e8 * 256.0;
+    return t >= 4.0e9 ? 4000000000u : (uint32_t)t;
+}
+
+// Compute units of the current device (cached per device).
+int device_cus();
 
 // The aligned vector kernel applies when every row's flat volume and stack
 // offsets keep one residue mod 4 across planes and the buffers are aligned.

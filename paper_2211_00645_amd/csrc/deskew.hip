@@ -61,15 +61,57 @@ extern "C" int dsk_plan(dsk_dims d, const double *offsets_px, double shift_px,
 
 namespace dsk {
 
+int device_cus() {
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev < 0 || dev >= 64) dev = 0;
+    if (cache[dev] <= 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            cus <= 0)
+            cus = 256;
+        cache[dev] = cus;
+    }
+    return cache[dev];
+}
+
+// Workgroups of the vector kernel one compute unit holds at once (cached
+// per kernel instance).
+template <typename TIn, int B, int G, int U, bool NT>
+static int vec_resident_per_cu() {
+    static int occ = 0;
+    if (occ <= 0) {
+        int o = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_forward_vec<TIn, B, G, U, NT>, B,
+                                                         0) != hipSuccess ||
+            o <= 0)
+            o = 1;
+        occ = o;
+    }
+    return occ;
+}
+
 template <typename TIn, int B, int PT, int U, bool NT>
-static hipError_t fwd_launch(const FwdArgs<TIn> &a, bool vec, int64_t tiles, int64_t edge,
+static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t edge, int pace_gbs,
                              hipStream_t s) {
     const dim3 block(B);
     if constexpr (PT >= 4) {
         if (vec) {
-            const dim3 grid((unsigned)(tiles * a.R + edge));
-            hipLaunchKernelGGL((k_forward_vec<TIn, B, PT / 4, U, NT>), grid, block, 0, s, a,
-                               (int)tiles);
+            auto kern = k_forward_vec<TIn, B, PT / 4, U, NT>;
+            const int64_t blocks = tiles * a.R + edge;
+            if (pace_gbs > 0) {
+                // one workgroup's share of a plane's bytes, timed at pace_gbs
+                const double plane_bytes = (double)a.R * a.C * sizeof(TIn) +
+                                           (a.vol ? 4.0 * (double)a.R * (double)a.W : 0.0);
+                const double t = plane_bytes / (double)blocks / ((double)pace_gbs * 1e9) * 1e8 *
+                                 65536.0;
+                a.tau_wg = t >= 4.0e9 ? 4000000000u : (uint32_t)t;
+                const int64_t cap =
+                    (int64_t)vec_resident_per_cu<TIn, B, PT / 4, U, NT>() * device_cus();
+                a.pace_cap = (int32_t)(cap < 1 ? 1 : (cap > kMaxI32 ? kMaxI32 : cap));
+            }
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), block, 0, s, a, (int)tiles);
             return hipGetLastError();
         }
     }
@@ -80,10 +122,10 @@ static hipError_t fwd_launch(const FwdArgs<TIn> &a, bool vec, int64_t tiles, int
 
 template <typename TIn>
 static hipError_t fwd_dispatch(const FwdArgs<TIn> &a, const dsk_tune &t, bool vec, int64_t tiles,
-                               int64_t edge, hipStream_t s) {
+                               int64_t edge, hipStream_t stream) {
     return dispatch_tune(t, [&](auto B, auto P, auto U, auto NT) {
         return fwd_launch<TIn, decltype(B)::value, decltype(P)::value, decltype(U)::value,
-                          decltype(NT)::value>(a, vec, tiles, edge, s);
+                          decltype(NT)::value>(a, vec, tiles, edge, t.pace_gbs, stream);
     });
 }
 
@@ -102,11 +144,11 @@ int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs
     hipError_t e;
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
-                         width, d.planes, d.rows, d.cols};
+                         width, d.planes, d.rows, d.cols, 0u, 0u, 0};
         e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
-                            width, d.planes, d.rows, d.cols};
+                            width, d.planes, d.rows, d.cols, 0u, 0u, 0};
         e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);

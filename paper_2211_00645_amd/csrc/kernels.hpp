@@ -126,7 +126,34 @@ struct FwdArgs {
     double shift, origin;
     int64_t W;
     int32_t N, R, C;
+    // Plane pacing.  Batch launches give the period directly (tau256, in
+    // 1/256 ticks of the 100 MHz real-time clock).  Plain launches give one
+    // workgroup's share of a plane's time (tau_wg, 1/65536 ticks) and the
+    // workgroups resident at once (pace_cap): workgroups start in id order
+    // in batches of pace_cap, and a batch of m workgroups moves one plane
+    // every m * tau_wg.  pace_cap = 0 and tau256 = 0: no pacing.
+    uint32_t tau256;
+    uint32_t tau_wg;
+    int32_t pace_cap;
 };
+
+// Plane pacing: a wavefront that reaches plane n before t0 + n * tau sleeps
+// until then (at most kPaceSleeps short sleeps, so it never stalls for long
+// and never depends on another wavefront).  Wavefronts left to themselves
+// drift hundreds of planes apart, which scatters the write stream over the
+// whole volume; pacing keeps them on neighbouring planes.
+constexpr int kPaceSleeps = 4096;
+
+__device__ __forceinline__ uint64_t pace_clock() { return __builtin_amdgcn_s_memrealtime(); }
+
+__device__ __forceinline__ void pace_until(uint64_t t0, uint32_t tau256, int n) {
+    if (tau256 == 0) return;
+    const uint64_t target = t0 + (((uint64_t)n * tau256) >> 8);
+    for (int i = 0; i < kPaceSleeps; ++i) {
+        if (pace_clock() >= target) break;
+        __builtin_amdgcn_s_sleep(2);
+    }
+}
 
 // Spread consecutive workgroup ids, which the dispatcher deals round-robin
 // to the 8 XCDs, so that each XCD receives a contiguous range of logical
@@ -313,6 +340,8 @@ struct VecTile {
     float *op0;                        // volume row r of plane 0 (or null)
     int gi[G], gfirst[G], glast[G];
     bool alive;
+    uint64_t t0;                       // pacing origin (this wavefront's start)
+    uint32_t tau;                      // pacing period, 1/256 ticks (0 = none)
     double acc[G][4];
     float mx[G][4];
     // chunk lane data (plane c0 + lane)
@@ -341,6 +370,14 @@ struct VecTile {
         last_special = ((int64_t)(N - 1) * rstep + (int64_t)r * C + C + 8 > total) ? N - 1 : -1;
         rp0 = a.in + (int64_t)r * C;
         op0 = a.vol ? a.vol + (int64_t)r * W : nullptr;
+        tau = a.tau256;
+        if (a.pace_cap > 0) {
+            const int64_t cap = a.pace_cap, batch = (int64_t)blockIdx.x / cap;
+            const int64_t left = (int64_t)gridDim.x - batch * cap;
+            const uint64_t t = ((uint64_t)a.tau_wg * (uint64_t)(left < cap ? left : cap)) >> 8;
+            tau = t > 4000000000ull ? 4000000000u : (uint32_t)t;
+        }
+        t0 = tau ? pace_clock() : 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int w0 = base + 64 * wv + BLOCK * g;
@@ -439,7 +476,7 @@ struct VecTile {
     // compiler counts the stores and the wait for the loads leaves them in
     // flight: stores never hold up the plane loop.
     template <int U, bool MASK, bool VOL>
-    __device__ __forceinline__ void pipe_loop(int g, int cn, const TIn *rpc, float *op) {
+    __device__ __forceinline__ void pipe_loop(int g, int c0, int cn, const TIn *rpc, float *op) {
         const int groups = cn / U;
         float *o = VOL ? op + xcol(g) : nullptr;
         if (groups > 0) {
@@ -450,6 +487,8 @@ struct VecTile {
             for (int k = 0; k < groups; ++k) {
                 RawWin<TIn> nxt[U];
                 issue<U, MASK>(g, (k + 1) * U, cn, rpc, nxt);
+                // a paced wavefront sleeps with the next loads in flight
+                pace_until(t0, tau, c0 + k * U);
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     float d[4];
@@ -537,16 +576,17 @@ struct VecTile {
                     if (op) {
                         float *o = op + xcol(g);
                         for (int li = 0; li < cn; ++li) {
+                            if ((li & 3) == 0) pace_until(t0, tau, c0 + li);
                             store_f32x4<NT>(o, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
                             o += ostep;
                         }
                     }
                 } else if (bin == valid) {
-                    if (op) pipe_loop<UNR, false, true>(g, cn, rp, op);
-                    else pipe_loop<UNR, false, false>(g, cn, rp, op);
+                    if (op) pipe_loop<UNR, false, true>(g, c0, cn, rp, op);
+                    else pipe_loop<UNR, false, false>(g, c0, cn, rp, op);
                 } else {
-                    if (op) pipe_loop<UNR, true, true>(g, cn, rp, op);
-                    else pipe_loop<UNR, true, false>(g, cn, rp, op);
+                    if (op) pipe_loop<UNR, true, true>(g, c0, cn, rp, op);
+                    else pipe_loop<UNR, true, false>(g, c0, cn, rp, op);
                 }
             }
         }
@@ -650,8 +690,15 @@ __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x
     }
 }
 
+// One group per lane with a shallow plane pipeline (UNR <= 2) is built for
+// 8 wavefronts per SIMD, so that a 512-row stack's tiles are all resident at
+// once (plane pacing then holds every wavefront of the launch to one
+// schedule).
+constexpr int vec_waves_per_eu(int g, int unr) { return g == 1 && unr <= 2 ? 8 : 1; }
+
 template <typename TIn, int BLOCK, int G, int UNR, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_forward_vec(FwdArgs<TIn> a, int tiles_x) {
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR)) void k_forward_vec(FwdArgs<TIn> a,
+                                                                              int tiles_x) {
     fwd_vec_block<TIn, BLOCK, G, UNR, NT>(a, tiles_x, xcd_remap(blockIdx.x, gridDim.x));
 }
 
@@ -665,13 +712,14 @@ struct JobDev {
     int64_t tile_begin;  // first global tile index of this job
     int32_t N, R, C, tiles_x;
     int32_t vec, edge_blocks;
+    uint32_t tau256;     // plane pacing period (see FwdArgs)
 };
 
 // Persistent launch: workgroups stride over the concatenated tile lists of
 // all jobs (job-major).  Each tile runs exactly the code of the plain launch
 // for that job, so outputs are bitwise equal.
 template <int BLOCK, int PT, int UNR, bool NT>
-__global__ __launch_bounds__(BLOCK) void k_forward_jobs(const JobDev *__restrict__ jobs,
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR)) void k_forward_jobs(const JobDev *__restrict__ jobs,
                                                         int n_jobs, int64_t total_tiles) {
     const int64_t grid = gridDim.x;
     const int64_t me = blockIdx.x;
@@ -698,6 +746,9 @@ __global__ __launch_bounds__(BLOCK) void k_forward_jobs(const JobDev *__restrict
         a.N = jb.N;
         a.R = jb.R;
         a.C = jb.C;
+        a.tau256 = jb.tau256;
+        a.tau_wg = 0;
+        a.pace_cap = 0;
         const int64_t lt = t - jb.tile_begin;
         if constexpr (PT >= 4) {
             if (jb.vec) {

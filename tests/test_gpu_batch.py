@@ -80,7 +80,11 @@ def test_graph_replays_match_single_launches(small, tmp_path):
 @pytest.mark.parametrize("tune", [dict(block=64, per_thread=4, unroll=1, nt_store=0),
                                   dict(block=256, per_thread=8, unroll=2, nt_store=1),
                                   dict(block=128, per_thread=1, unroll=1, nt_store=0),
-                                  dict(block=128, per_thread=4, unroll=4, nt_store=1)])
+                                  dict(block=128, per_thread=4, unroll=4, nt_store=1),
+                                  dict(block=64, per_thread=4, unroll=4, nt_store=1,
+                                       pace_gbs=6000),
+                                  dict(block=64, per_thread=8, unroll=2, nt_store=1,
+                                       pace_gbs=300)])
 def test_every_shape_same_bits(small, tune):
     stacks, geoms = small
     b = Batch(stacks, geoms, tune=tune)

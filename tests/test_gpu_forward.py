@@ -90,6 +90,9 @@ def test_config1_fractional(cfg1):
 TUNES = [dict(block=b, per_thread=j, nt_store=nt, unroll=u)
          for b in (64, 128, 256) for j in (1, 2, 4, 8) for nt in (0, 1) for u in (1, 2, 4)
          if not (j < 4 and u > 1)]
+# plane pacing only delays wavefronts: slow, default and never-binding paces
+TUNES += [dict(block=b, per_thread=j, nt_store=1, unroll=4, pace_gbs=p)
+          for b in (64, 256) for j in (4, 8) for p in (500, 6000, 100000)]
 
 
 def test_every_launch_shape_is_bitwise_identical(cfg1):
