@@ -27,7 +27,8 @@ SEED, BLOBS = 2, 2000
 HBM_PEAK_GBS = 8000.0
 METRIC = "deskewed voxels/s & HBM GB/s, 512×512×2048 u16 stack; p99 live-stack latency"
 KERNEL_SOURCES = ["paper_2211_00645_amd/csrc/kernels.hpp",
-                  "paper_2211_00645_amd/csrc/deskew.hip"]
+                  "paper_2211_00645_amd/csrc/deskew.hip",
+                  "paper_2211_00645_amd/csrc/common.hpp"]
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "forward_512x512x2048_pmc.md")
 
 
@@ -187,6 +188,24 @@ def bench_autograd(torch, dsk, synth):
             "backward_ms": bwd, "backward_gbs": bb / bwd / 1e6}
 
 
+def bench_view(torch, dsk, synth):
+    """Shear-warp views of the 512 x 512 x 2048 stack: projections of the
+    re-sheared stack (no volume) plus the column stretch, per view angle."""
+    st = synth.blob_stack((N, R, C), BLOBS, SEED, device="cuda")
+    res = {"workload": "shear-warp views of the 512x512x2048 uint16 stack, 35 deg"}
+    for theta in (0.0, 20.0, ANGLE):
+        g = dsk.view_plan((N, R, C), theta, ANGLE, STEP, PIXEL)
+        ws = torch.empty((R * g["proj_width"] * 2,), dtype=torch.float32, device="cuda")
+        ms = _median_ms(torch, lambda: dsk.view(st, theta, ANGLE, STEP, PIXEL, workspace=ws), 10)
+        alg = 2 * N * R * C + 16 * R * g["proj_width"] + 8 * R * g["width"]
+        res[f"theta_{theta:g}"] = {"ms": ms, "gbs": alg / ms / 1e6, "shear_px": g["shear"],
+                                   "stretch": g["stretch"], "proj_width": g["proj_width"],
+                                   "view_width": g["width"], "algorithmic_bytes": alg}
+    del st
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(torch, dsk, synth, n_req, rate):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time."""
@@ -197,23 +216,22 @@ def bench_serving(torch, dsk, synth, n_req, rate):
             pool[(r, c, ch)] = synth.blob_stack((400, r, c), synth.blobs_for_volume(400, r, c),
                                                 500 + 2 * k + ch, device="cuda")
     torch.cuda.synchronize()
-    res = {"workload": f"{n_req} 2-channel stacks, Poisson {rate} Hz, 200 GB budget"}
-    # warm the allocator and the kernels
-    ex = sv.GPUExecutor(pool, n_slots=4)
-    sv.Scheduler(ex, 200 << 30, n_slots=4).run(sv.make_requests(synth.serving_trace(8, 1e6, 9)))
+    budget = 200 << 30
+    res = {"workload": f"{n_req} 2-channel stacks, Poisson {rate} Hz, 200 GiB budget"}
+    # one executor: its output arena is reserved once and reused by every run
+    ex = sv.GPUExecutor(pool, n_slots=4, arena_bytes=budget)
+    sv.Scheduler(ex, budget, n_slots=4).run(sv.make_requests(synth.serving_trace(8, 1e6, 9)))
     for mode in ("live", "burst"):
         r_ = rate if mode == "live" else 1e9
         tr = synth.serving_trace(n_req, r_, 7)
-        ex = sv.GPUExecutor(pool, n_slots=4)
-        sch = sv.Scheduler(ex, 200 << 30, n_slots=4, max_batch=8)
+        sch = sv.Scheduler(ex, budget, n_slots=4, max_batch=8)
         res[mode] = dict(sv.summarize(sch.run(sv.make_requests(tr))), launches=sch.launches,
-                         peak_gb=sch.peak_used / 1e9)
-        res[mode + "_plain"] = sv.summarize(sv.run_plain(sv.GPUExecutor(pool, n_slots=1),
-                                                         sv.make_requests(tr)))
+                         peak_gb=sch.peak_used / 1e9, space_waits=sch.space_waits)
+        res[mode + "_plain"] = sv.summarize(sv.run_plain(ex, sv.make_requests(tr)))
         log(f"serving {mode}: p50 {res[mode]['latency_p50_ms']:.2f} ms p99 "
             f"{res[mode]['latency_p99_ms']:.2f} ms; plain p99 "
             f"{res[mode + '_plain']['latency_p99_ms']:.2f} ms")
-    del pool
+    del pool, ex
     torch.cuda.empty_cache()
     return res
 
@@ -225,8 +243,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,serving",
-                    help="comma list of extra measurements (batch, autograd, serving) or none")
+    ap.add_argument("--extras", default="batch,autograd,view,serving",
+                    help="comma list of extra measurements (batch, autograd, view, serving) "
+                         "or none")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
@@ -310,6 +329,9 @@ def main():
     if "autograd" in extras:
         log("autograd: forward + backward")
         ext["autograd"] = bench_autograd(torch, dsk, synth)
+    if "view" in extras:
+        log("view: shear-warp rotated views")
+        ext["view"] = bench_view(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)

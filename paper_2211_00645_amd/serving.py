@@ -30,6 +30,8 @@ from typing import Any, Dict, List, Optional
 
 import numpy as np
 
+from .arena import Arena, NoSpace
+
 
 @dataclass
 class Request:
@@ -113,6 +115,7 @@ class Scheduler:
         self.peak_used = 0
         self.launches = 0
         self.max_inflight = 0
+        self.space_waits = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
         arrivals = sorted(requests, key=lambda r: r.t_arrival)
@@ -169,6 +172,19 @@ class Scheduler:
                     r.status = "running"
                 try:
                     tok = self.ex.submit(slot, batch)
+                except NoSpace:
+                    # the executor's memory is fragmented: the batch goes back
+                    # to the head of the queue until a completion frees space
+                    for r in reversed(batch):
+                        r.status = "queued"
+                        r.t_admit = math.nan
+                        queue.appendleft(r)
+                    self.used -= nb
+                    free.append(slot)
+                    self.space_waits += 1
+                    if not inflight:
+                        raise RuntimeError("executor has no space with nothing in flight")
+                    break
                 except Exception:
                     for r in batch:
                         r.status = "failed"
@@ -247,7 +263,7 @@ class MockExecutor:
     report failure."""
 
     def __init__(self, clock: FakeClock, s_per_byte: float = 1e-10, width_fn=None,
-                 fail_rids=()):
+                 fail_rids=(), arena_bytes=None):
         self.clock = clock
         self.s_per_byte = s_per_byte
         self.width_fn = width_fn or (lambda r: r.cols + r.planes)
@@ -255,15 +271,17 @@ class MockExecutor:
         self.pending: Dict[int, tuple] = {}
         self.k = 0
         self.submitted: List[List[int]] = []
+        self.arena = Arena(arena_bytes, align=1) if arena_bytes else None
 
     def width(self, r):
         return self.width_fn(r)
 
     def submit(self, slot, reqs):
         nb = sum(r.nbytes for r in reqs)
+        off = self.arena.alloc(nb) if self.arena else None
         t_end = self.clock.now() + nb * self.s_per_byte
         self.k += 1
-        self.pending[self.k] = (t_end, [r.rid for r in reqs])
+        self.pending[self.k] = (t_end, [r.rid for r in reqs], off)
         self.submitted.append([r.rid for r in reqs])
         return self.k
 
@@ -274,7 +292,9 @@ class MockExecutor:
         return min(v[0] for v in self.pending.values()) if self.pending else None
 
     def finish(self, tok):
-        _, rids = self.pending.pop(tok)
+        _, rids, off = self.pending.pop(tok)
+        if off is not None:
+            self.arena.free(off)
         return not (set(rids) & self.fail)
 
 
@@ -284,49 +304,100 @@ class GPUExecutor:
     [cols] tensor; a request uses its first ``planes`` planes), standing in
     for camera frames already delivered to HBM.  Each submit is ONE
     persistent launch over all channels of all requests in the batch on the
-    slot's stream, followed by the projections' copy to pinned host memory
-    and an event."""
+    slot's stream, followed by the projections' copy to the slot's pinned
+    staging buffer and an event.
 
-    def __init__(self, pool, n_slots=4, tune=None, keep_volume=True, max_jobs=64):
+    Outputs live in one device arena of ``arena_bytes`` reserved up front
+    (first fit, freed at completion; :class:`NoSpace` when fragmented), so
+    the loop never allocates device memory per request.  With
+    ``keep_results`` the outputs are allocated separately instead and kept
+    with the request (for checking)."""
+
+    def __init__(self, pool, n_slots=4, tune=None, keep_volume=True, max_jobs=64,
+                 arena_bytes=8 << 30):
         import torch
         from .batch import JobLauncher
         self.torch = torch
         self.pool = pool
         self.tune = tune
         self.keep_volume = keep_volume
-        self.streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        dev = next(iter(pool.values())).device
+        self.device = dev
+        self.streams = [torch.cuda.Stream(device=dev) for _ in range(n_slots)]
         self.launcher = JobLauncher(max_jobs=max_jobs, slots=2 * n_slots)
         self.keep_results = False
+        self.arena = Arena(arena_bytes, align=256)
+        self.buf = None                            # reserved on first use
+        self.staging = [None] * n_slots           # pinned float32 host buffers
 
     def width(self, r):
         from . import api
         return api.plan((r.planes, r.rows, r.cols),
                         shift=api.shift_px(r.angle_deg, r.step_um, r.pixel_um))[0]
 
+    def _outputs(self, reqs):
+        """(request, channel, n, rows, width) per job and the arena bytes."""
+        items, total = [], 0
+        for r in reqs:
+            w = self.width(r)
+            for ch in range(r.channels):
+                items.append((r, ch, r.planes, r.rows, w))
+                nb = 8 * r.rows * w + (4 * r.planes * r.rows * w if self.keep_volume else 0)
+                total += self.arena.round(nb)
+        return items, total
+
+    def _view(self, base, off, shape):
+        n = 1
+        for v in shape:
+            n *= v
+        return self.buf[base + off: base + off + 4 * n].view(self.torch.float32).view(shape)
+
     def submit(self, slot, reqs):
         from .batch import plan_job
         torch = self.torch
         s = self.streams[slot]
-        jobs, outs = [], []
+        items, total = self._outputs(reqs)
+        base = None
+        if not self.keep_results:
+            if self.buf is None:
+                self.buf = torch.empty((self.arena.size,), dtype=torch.uint8, device=self.device)
+            base = self.arena.alloc(total)        # raises NoSpace when fragmented
+        proj = sum(2 * rows * w for (_, _, _, rows, w) in items)
+        st = self.staging[slot]
+        if st is None or st.numel() < proj:
+            st = torch.empty((max(proj, 1 << 20),), dtype=torch.float32, pin_memory=True)
+            self.staging[slot] = st
+        jobs, outs, host = [], [], []
+        off = 0
+        hoff = 0
         with torch.cuda.stream(s):
-            for r in reqs:
-                for ch in range(r.channels):
-                    stack = self.pool[(r.rows, r.cols, ch)][:r.planes]
-                    job, res = plan_job(stack, r.angle_deg, r.step_um, r.pixel_um,
-                                        vol=self.keep_volume)
-                    jobs.append(job)
-                    outs.append((r, ch, res))
+            for (r, ch, n, rows, w) in items:
+                stack = self.pool[(r.rows, r.cols, ch)][:r.planes]
+                out = None
+                if base is not None:
+                    out = {"psum": self._view(base, off, (rows, w)),
+                           "pmax": self._view(base, off + 4 * rows * w, (rows, w))}
+                    nb = 8 * rows * w
+                    if self.keep_volume:
+                        out["vol"] = self._view(base, off + nb, (n, rows, w))
+                        nb += 4 * n * rows * w
+                    off += self.arena.round(nb)
+                job, res = plan_job(stack, r.angle_deg, r.step_um, r.pixel_um,
+                                    vol=self.keep_volume, out=out)
+                jobs.append(job)
+                outs.append((r, ch, res))
             self.launcher.launch(jobs, self.tune, stream=s)
-            host = []
             for r, ch, res in outs:
-                hp = torch.empty(res["psum"].shape, dtype=torch.float32, pin_memory=True)
-                hm = torch.empty(res["pmax"].shape, dtype=torch.float32, pin_memory=True)
+                m = res["psum"].numel()
+                hp = st[hoff: hoff + m].view(res["psum"].shape)
+                hm = st[hoff + m: hoff + 2 * m].view(res["pmax"].shape)
+                hoff += 2 * m
                 hp.copy_(res["psum"], non_blocking=True)
                 hm.copy_(res["pmax"], non_blocking=True)
                 host.append((hp, hm))
             ev = torch.cuda.Event()
             ev.record(s)
-        return (ev, outs, host)
+        return (ev, outs, host, base)
 
     def done(self, tok):
         return tok[0].query()
@@ -335,13 +406,15 @@ class GPUExecutor:
         return None
 
     def finish(self, tok):
-        ev, outs, host = tok
+        ev, outs, host, base = tok
         ev.synchronize()
         for (r, ch, res), (hp, hm) in zip(outs, host):
             if r.result is None:
                 r.result = {}
-            keep = {"psum": hp, "pmax": hm}
+            keep = {"psum": hp.clone(), "pmax": hm.clone()}
             if self.keep_results and "vol" in res:
                 keep["vol"] = res["vol"]
             r.result[ch] = keep
+        if base is not None:
+            self.arena.free(base)
         return True

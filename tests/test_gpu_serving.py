@@ -76,3 +76,26 @@ def test_budget_holds_and_plain_baseline(pool):
     _check_alone(pool, done)
     plain = run_plain(GPUExecutor(pool, n_slots=1), _trace(10, 5000.0, 2))
     assert all(r.status == "done" for r in plain)
+
+
+def test_arena_outputs_equal_solo_runs(pool):
+    """Outputs placed in the executor's arena (here only about three
+    requests large, so batches also wait for space): projections bitwise
+    equal to solo runs."""
+    from paper_2211_00645_amd.serving import request_bytes
+    reqs = _trace(30, 4000.0, 3)
+    probe = GPUExecutor(pool, n_slots=1)
+    one = max(request_bytes(r, probe.width(r)) for r in reqs)
+    ex = GPUExecutor(pool, n_slots=3, arena_bytes=3 * one)
+    sch = Scheduler(ex, budget_bytes=3 * one, n_slots=3, max_batch=4)
+    done = sch.run(reqs)
+    print(f"arena: launches={sch.launches} space_waits={sch.space_waits}", flush=True)
+    assert all(r.status == "done" for r in done)
+    assert ex.arena.used == 0
+    for r in done:
+        for ch in range(2):
+            solo = dsk.deskew(pool[(r.rows, r.cols, ch)][:r.planes], r.angle_deg, r.step_um,
+                              r.pixel_um)
+            torch.cuda.synchronize()
+            assert torch.equal(r.result[ch]["psum"], solo["psum"].cpu()), (r.rid, ch)
+            assert torch.equal(r.result[ch]["pmax"], solo["pmax"].cpu()), (r.rid, ch)

@@ -129,3 +129,26 @@ def test_make_requests_from_trace():
     mean_gap = (ts[-1] - ts[0]) / 49
     assert 0.02 < mean_gap < 0.1          # Poisson at 20 Hz
     assert not math.isnan(reqs[0].t_arrival)
+
+
+def test_fragmented_executor_memory_requeues_batch():
+    """The executor places outputs in an arena as large as the budget; when
+    a batch fits the budget but no contiguous block, it goes back to the
+    head of the queue and runs once a completion frees space."""
+    import random
+    rnd = random.Random(5)
+    clk = FakeClock()
+    reqs = [Request(rid=i, t_arrival=0.0005 * i, planes=rnd.choice([20, 60, 140]), rows=64,
+                    cols=64, channels=2) for i in range(80)]
+    big = max(request_bytes(r, r.cols + r.planes) for r in reqs)
+    budget = 3 * big
+    ex = MockExecutor(clk, s_per_byte=1e-9, arena_bytes=budget)
+    sch = Scheduler(ex, budget_bytes=budget, n_slots=4, max_batch=2, clock=clk)
+    done = sch.run(reqs)
+    assert all(r.status == "done" for r in done) and len(done) == 80
+    assert sch.space_waits > 0
+    assert sch.peak_used <= budget and sch.used == 0
+    assert ex.arena.used == 0
+    # FIFO order of admission is kept across the requeues
+    flat = [rid for b in ex.submitted for rid in b]
+    assert sorted(set(flat)) == list(range(80))
