@@ -107,6 +107,21 @@ int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float *vol,
                    float *psum, float *pmax, int64_t out_width,
                    hipStream_t stream);
 
+/* One colour channel of multi-channel camera frames (methods section: each
+ * raw image is split into its colour channels and every channel is deskewed
+ * on its own), read in place without a split copy.  frames: DEVICE uint16
+ * [d.planes][d.rows][frame_cols]; the channel is the column range
+ * [col0, col0 + d.cols) of every frame row (the camera's region layout is
+ * the caller's: the paper does not fix it).  Geometry, outputs and
+ * out_width as dsk_deskew_u16; the result is bitwise that of
+ * dsk_deskew_u16 on the channel copied to a dense stack.  DSK_EINVAL if the
+ * range leaves the frame.  Launch channels on separate streams to overlap
+ * them. */
+int dsk_deskew_channel_u16(const uint16_t *frames, int64_t frame_cols,
+                           int64_t col0, dsk_dims d, dsk_geom g, float *vol,
+                           float *psum, float *pmax, int64_t out_width,
+                           hipStream_t stream);
+
 /* As dsk_deskew_u16 with explicit per-image offsets (pixels).  offsets_dev:
  * DEVICE array of d.planes FP64 offsets (scan jitter, autograd).  origin
  * (b) and out_width (> 0) are explicit, so the grid can stay fixed while

@@ -7,8 +7,8 @@ views -- runs in the HIP kernels of
 ``libdeskew.so`` (C ABI in ``include/deskew.h``).  Import is light: the
 library is loaded on first use and its absence is an error, never a fallback.
 """
-from .api import (adjoint, backward, deskew, plan, shear_grad, shift_px, stretch,  # noqa: F401
-                  view, view_plan)
+from .api import (adjoint, backward, deskew, deskew_channels, plan, shear_grad,  # noqa: F401
+                  shift_px, stretch, view, view_plan)
 
-__all__ = ["deskew", "plan", "shift_px", "backward", "adjoint", "shear_grad", "view",
-           "view_plan", "stretch"]
+__all__ = ["deskew", "deskew_channels", "plan", "shift_px", "backward", "adjoint",
+           "shear_grad", "view", "view_plan", "stretch"]

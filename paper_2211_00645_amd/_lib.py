@@ -50,6 +50,8 @@ _SIGS = {
     "dsk_plan": (ctypes.c_int, [Dims, c_vp, c_dbl, ctypes.POINTER(c_i64),
                                 ctypes.POINTER(c_i64)]),
     "dsk_deskew_u16": (ctypes.c_int, [c_vp, Dims, Geom, c_vp, c_vp, c_vp, c_i64, c_vp]),
+    "dsk_deskew_channel_u16": (ctypes.c_int, [c_vp, c_i64, c_i64, Dims, Geom, c_vp, c_vp, c_vp,
+                                              c_i64, c_vp]),
     "dsk_deskew_offsets_u16": (ctypes.c_int, [c_vp, Dims, c_vp, c_i64, c_vp, c_vp, c_vp,
                                               c_i64, c_vp]),
     "dsk_deskew_offsets_f32": (ctypes.c_int, [c_vp, Dims, c_vp, c_i64, c_vp, c_vp, c_vp,

@@ -268,3 +268,49 @@ def stretch(proj, factor, width=None, stream=None):
                                  _stream(stream))
     L.check(st, "dsk_stretch_f32")
     return out
+
+
+def deskew_channels(frames, col0s, cols, angle_deg, step_um, pixel_um, *, vol=True, psum=True,
+                    pmax=True, streams=None):
+    """Deskew the colour channels of multi-channel camera frames (each raw
+    image split into its channels, every channel deskewed on its own),
+    reading each channel in place.  ``frames``: contiguous uint16 CUDA
+    tensor [planes][rows][frame_cols]; channel k is columns
+    [col0s[k], col0s[k] + cols).  Channel k runs on ``streams[k]`` (default:
+    one new stream per channel, joined back to the current stream).
+    Returns one result dict per channel, as :func:`deskew`."""
+    _check_stack(frames, (torch.uint16,))
+    n, r, fc = (int(v) for v in frames.shape)
+    cols = int(cols)
+    dims = L.Dims(n, r, cols)
+    geom = L.Geom(angle_deg, step_um, pixel_um)
+    w, b = plan((n, r, cols), shift=shift_px(angle_deg, step_um, pixel_um))
+    cur = torch.cuda.current_stream(frames.device)
+    own = streams is None
+    if own:
+        streams = [torch.cuda.Stream(device=frames.device) for _ in col0s]
+    lib = L.lib()
+    out = []
+    for k, c0 in enumerate(col0s):
+        s = streams[k]
+        if own:
+            s.wait_stream(cur)
+        res = {"origin": b, "width": w, "col0": int(c0)}
+        with torch.cuda.stream(s):
+            for key, want, shp in (("vol", vol, (n, r, w)), ("psum", psum, (r, w)),
+                                   ("pmax", pmax, (r, w))):
+                if want:
+                    res[key] = torch.empty(shp, dtype=torch.float32, device=frames.device)
+        st = lib.dsk_deskew_channel_u16(_vp(frames), fc, int(c0), dims, geom, _vp(res.get("vol")),
+                                        _vp(res.get("psum")), _vp(res.get("pmax")), 0,
+                                        ctypes.c_void_p(s.cuda_stream))
+        L.check(st, "dsk_deskew_channel_u16")
+        out.append(res)
+    if own:
+        for s in streams:
+            cur.wait_stream(s)
+        for res in out:
+            for key in ("vol", "psum", "pmax"):
+                if key in res:
+                    res[key].record_stream(cur)
+    return out

@@ -52,7 +52,8 @@ int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out)
     int64_t begin = 0;
     for (int i = 0; i < n; ++i) {
         const dsk_job &j = jobs[i];
-        const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol);
+        const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol,
+                                (int64_t)j.dims.rows * j.dims.cols);
         const int64_t tx = tiles_x(j.out_width, t, vec);
         const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec);
         if (tx > kMaxI32) return -1;

@@ -45,11 +45,11 @@ int device_cus();
 // The aligned vector kernel applies when every row's flat volume and stack
 // offsets keep one residue mod 4 across planes and the buffers are aligned.
 inline bool vec_ok(const dsk_tune &t, dsk_dims d, int64_t width, const void *in, int in_is_f32,
-                   const float *vol) {
+                   const float *vol, int64_t in_plane) {
     if (t.per_thread < 4) return false;
-    if ((int64_t)d.planes * d.rows * d.cols < 64 || (int64_t)d.rows * d.cols < 8) return false;
+    if ((int64_t)d.planes * d.rows * d.cols < 64 || in_plane < 8) return false;
     if (width >= (int64_t(1) << 27) || d.cols >= (1 << 27)) return false;
-    if (((int64_t)d.rows * width) % 4 != 0 || ((int64_t)d.rows * d.cols) % 4 != 0) return false;
+    if (((int64_t)d.rows * width) % 4 != 0 || in_plane % 4 != 0) return false;
     const uintptr_t ia = in_is_f32 ? 15 : 7;
     if ((uintptr_t)in & ia) return false;
     if (vol && ((uintptr_t)vol & 15)) return false;
@@ -117,9 +117,23 @@ inline int check_frame(dsk_dims d, int64_t origin, int64_t width) {
 
 inline int hip_status(hipError_t e) { return e == hipSuccess ? DSK_OK : DSK_EHIP; }
 
-// Launchers (deskew.hip) used by the batch translation unit.
+// Input layout in elements (see FwdArgs): row pitch, plane pitch and the
+// readable extent [in - lo, in + hi).
+struct InLayout {
+    int64_t row, plane, lo, hi;
+};
+
+inline InLayout dense_layout(dsk_dims d) {
+    return InLayout{d.cols, (int64_t)d.rows * d.cols, 0, (int64_t)d.planes * d.rows * d.cols};
+}
+
+// Launchers (deskew.hip) used by the other translation units.
 int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs,
                    double shift, int64_t origin, float *vol, float *psum, float *pmax,
                    int64_t width, const dsk_tune &t, hipStream_t stream);
+int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLayout &lay,
+                          const double *offs, double shift, int64_t origin, float *vol,
+                          float *psum, float *pmax, int64_t width, const dsk_tune &t,
+                          hipStream_t stream);
 
 }  // namespace dsk

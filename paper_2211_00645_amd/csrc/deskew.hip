@@ -129,29 +129,45 @@ static hipError_t fwd_dispatch(const FwdArgs<TIn> &a, const dsk_tune &t, bool ve
     });
 }
 
-int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs, double shift,
-                   int64_t origin, float *vol, float *psum, float *pmax, int64_t width,
-                   const dsk_tune &t, hipStream_t stream) {
+int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLayout &lay,
+                          const double *offs, double shift, int64_t origin, float *vol,
+                          float *psum, float *pmax, int64_t width, const dsk_tune &t,
+                          hipStream_t stream) {
     if (!in || !dims_ok(d) || (!vol && !psum && !pmax)) return DSK_EINVAL;
     if (!offs && !std::isfinite(shift)) return DSK_EINVAL;
     if (!tune_ok(t)) return DSK_EINVAL;
     int st = check_frame(d, origin, width);
     if (st != DSK_OK) return st;
-    const bool vec = vec_ok(t, d, width, in, in_is_f32, vol);
+    // every row must lie inside the readable extent
+    const int64_t last = (int64_t)(d.planes - 1) * lay.plane + (int64_t)(d.rows - 1) * lay.row;
+    if (lay.row < d.cols || lay.plane < (int64_t)(d.rows - 1) * lay.row + d.cols || lay.lo < 0 ||
+        lay.hi < last + d.cols)
+        return DSK_ESHAPE;
+    const bool vec = vec_ok(t, d, width, in, in_is_f32, vol, lay.plane);
     const int64_t tiles = tiles_x(width, t, vec);
     const int64_t edge = edge_blocks(d, width, t, vec);
     if (tiles * (int64_t)d.rows + edge > kMaxI32) return DSK_ESHAPE;
     hipError_t e;
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
-                         width, d.planes, d.rows, d.cols, 0u, 0u, 0};
+                         width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
+                         0u, 0u, 0};
         e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
-                            width, d.planes, d.rows, d.cols, 0u, 0u, 0};
+                            width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
+                            0u, 0u, 0};
         e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);
+}
+
+int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs, double shift,
+                   int64_t origin, float *vol, float *psum, float *pmax, int64_t width,
+                   const dsk_tune &t, hipStream_t stream) {
+    if (!dims_ok(d)) return DSK_EINVAL;
+    return launch_forward_layout(in, in_is_f32, d, dense_layout(d), offs, shift, origin, vol,
+                                 psum, pmax, width, t, stream);
 }
 
 }  // namespace dsk
@@ -168,6 +184,25 @@ extern "C" int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float 
     if (st != DSK_OK) return st;
     if (out_width > 0) w = out_width;
     return launch_forward(in, 0, d, nullptr, s, b, vol, psum, pmax, w, kDefaultTune, stream);
+}
+
+extern "C" int dsk_deskew_channel_u16(const uint16_t *frames, int64_t frame_cols, int64_t col0,
+                                      dsk_dims d, dsk_geom g, float *vol, float *psum,
+                                      float *pmax, int64_t out_width, hipStream_t stream) {
+    if (!frames || !dims_ok(d) || out_width < 0 || col0 < 0 || frame_cols < col0 + d.cols)
+        return DSK_EINVAL;
+    if (frame_cols >= (int64_t(1) << 30)) return DSK_ESHAPE;
+    double s = 0.0;
+    int st = dsk_shift_px(g, &s);
+    if (st != DSK_OK) return st;
+    int64_t w = 0, b = 0;
+    st = dsk_plan(d, nullptr, s, &w, &b);
+    if (st != DSK_OK) return st;
+    if (out_width > 0) w = out_width;
+    const int64_t plane = (int64_t)d.rows * frame_cols;
+    const InLayout lay{frame_cols, plane, col0, (int64_t)d.planes * plane - col0};
+    return launch_forward_layout(frames + col0, 0, d, lay, nullptr, s, b, vol, psum, pmax, w,
+                                 kDefaultTune, stream);
 }
 
 extern "C" int dsk_deskew_offsets_u16(const uint16_t *in, dsk_dims d, const double *offsets_dev,

@@ -126,6 +126,11 @@ struct FwdArgs {
     double shift, origin;
     int64_t W;
     int32_t N, R, C;
+    // Input layout in elements: row pitch, plane pitch, and the readable
+    // extent around `in` ([in - in_lo, in + in_hi)).  A dense stack has
+    // (C, R*C, 0, N*R*C); a channel of a wider camera frame has the frame's
+    // pitches and the frame's extent.
+    int64_t in_row, in_plane, in_lo, in_hi;
     // Plane pacing.  Batch launches give the period directly (tau256, in
     // 1/256 ticks of the 100 MHz real-time clock).  Plain launches give one
     // workgroup's share of a plane's time (tau_wg, 1/65536 ticks) and the
@@ -184,7 +189,7 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
     for (int n = 0; n < a.N; ++n) {
         const PlaneCoef pc = cc.get(n);
         const int64_t rowi = (int64_t)n * a.R + r;
-        const TIn *row = a.in + rowi * C;
+        const TIn *row = a.in + (int64_t)n * a.in_plane + (int64_t)r * a.in_row;
         float *orow = a.vol ? a.vol + rowi * W : nullptr;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -335,7 +340,7 @@ struct VecTile {
     // 4-aligned 8-element window inside the stack, away from its two ends
     int lo_off, hi_off;
     int first_special, last_special;   // planes whose row lies at a stack end
-    int64_t rstep, ostep, total;
+    int64_t rstep, ostep;
     const TIn *rp0;                    // row r of plane 0
     float *op0;                        // volume row r of plane 0 (or null)
     int gi[G], gfirst[G], glast[G];
@@ -353,22 +358,23 @@ struct VecTile {
         const RowGeo rg = row_geo(r, W);
         ca = rg.ca;
         ng = rg.ng;
-        total = (int64_t)N * a.R * C;
-        rstep = (int64_t)a.R * C;
+        rstep = a.in_plane;
         ostep = (int64_t)a.R * W;
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
         lane = (int)threadIdx.x & 63;
         const int base = tile * BLOCK * G;
         alive = base + 64 * wv < ng;
-        // rows*C is a multiple of 4, so every plane's row start has this residue
-        gmod = (int)(((int64_t)r * C) & 3);
+        // the plane pitch is a multiple of 4, so every plane's row start has
+        // this residue
+        gmod = (int)(((int64_t)r * a.in_row) & 3);
         lo_off = -8 + ((-gmod) & 3);
         hi_off = C - 1 - ((C - 1 + gmod) & 3);
-        // rows*C >= 8: only plane 0 can start closer than 8 elements to the
-        // stack start and only plane N-1 can end closer than 8 to its end
-        first_special = ((int64_t)r * C < 8) ? 0 : -1;
-        last_special = ((int64_t)(N - 1) * rstep + (int64_t)r * C + C + 8 > total) ? N - 1 : -1;
-        rp0 = a.in + (int64_t)r * C;
+        // plane pitch >= 8: only plane 0 can start closer than 8 elements to
+        // the readable start and only plane N-1 can end closer than 8 to its end
+        const int64_t g0 = (int64_t)r * a.in_row;
+        first_special = (g0 - 8 < -a.in_lo) ? 0 : -1;
+        last_special = ((int64_t)(N - 1) * rstep + g0 + C + 8 > a.in_hi) ? N - 1 : -1;
+        rp0 = a.in + (int64_t)r * a.in_row;
         op0 = a.vol ? a.vol + (int64_t)r * W : nullptr;
         tau = a.tau256;
         if (a.pace_cap > 0) {
@@ -531,8 +537,9 @@ struct VecTile {
             int lo = lo_off, hi = hi_off;
             if (n == first_special || n == last_special) {
                 const int64_t grow = rp - a.in;
-                lo = (int)(-grow > (int64_t)lo ? -grow : (int64_t)lo);
-                hi = (int)(total - 8 - grow < (int64_t)hi ? total - 8 - grow : (int64_t)hi);
+                const int64_t lo_ok = -grow - a.in_lo, hi_ok = a.in_hi - 8 - grow;
+                lo = (int)(lo_ok > (int64_t)lo ? lo_ok : (int64_t)lo);
+                hi = (int)(hi_ok < (int64_t)hi ? hi_ok : (int64_t)hi);
             }
             const int off = p - sh;
             const int oc = off < lo ? lo : (off > hi ? hi : off);
@@ -618,8 +625,8 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
     int x = edge_col(rg, W, e - 6 * (e / 6));
     for (int j = 0; j < 6 && x < 0; ++j) x = edge_col(rg, W, j);
     if (x < 0) x = 0;   // unreachable when W % 4 != 0
-    const int64_t rstep = (int64_t)a.R * C, ostep = (int64_t)a.R * W;
-    const TIn *rp = a.in + (int64_t)r * C;
+    const int64_t rstep = a.in_plane, ostep = (int64_t)a.R * W;
+    const TIn *rp = a.in + (int64_t)r * a.in_row;
     float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
     CoefCache cc;
     cc.init(a.offs, a.shift, a.origin, a.N);
@@ -746,6 +753,10 @@ __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR)) void
         a.N = jb.N;
         a.R = jb.R;
         a.C = jb.C;
+        a.in_row = jb.C;
+        a.in_plane = (int64_t)jb.R * jb.C;
+        a.in_lo = 0;
+        a.in_hi = (int64_t)jb.N * jb.R * jb.C;
         a.tau256 = jb.tau256;
         a.tau_wg = 0;
         a.pace_cap = 0;

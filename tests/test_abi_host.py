@@ -149,3 +149,15 @@ def test_view_entry_points_reject_bad_arguments_before_any_launch():
                             320, None) == L.DSK_EINVAL
     assert lib.dsk_stretch_f32(fake, 2, 20, float("inf"), fake, 18, None) == L.DSK_EINVAL
     assert lib.dsk_stretch_f32(fake, 2, 20, 0.9, None, 18, None) == L.DSK_EINVAL
+
+
+def test_channel_entry_point_rejects_ranges_outside_the_frame():
+    lib = L.lib()
+    d = L.Dims(4, 2, 8)
+    g = L.Geom(30.0, 0.4, 0.115)
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.dsk_deskew_channel_u16(None, 16, 0, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_channel_u16(fake, 16, 9, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_channel_u16(fake, 16, -1, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_channel_u16(fake, 7, 0, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
+    assert lib.dsk_deskew_channel_u16(fake, 16, 8, d, g, None, None, None, 0, None) == L.DSK_EINVAL
