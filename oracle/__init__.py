@@ -16,6 +16,9 @@ Every function here follows the paper's definitions, cited per function:
   * ``view_geometry``, ``warp``, ``view`` -- the shear-warp rotated view
                       (Fig. 3): projection of the stack remapped with a
                       changed shift, stretched along the column axis.
+  * ``affine_frame``, ``affine`` -- the real-space (affine) deskew the paper
+                      contrasts the remap with: the stack resampled onto a
+                      Cartesian grid by interpolation between images.
 """
 import ctypes
 import os
@@ -64,6 +67,12 @@ def _load():
     lib.orc_view_width.argtypes = [_i64, ctypes.c_double]
     lib.orc_warp.restype = None
     lib.orc_warp.argtypes = [_dp, _i64, _i64, ctypes.c_double, _i64, _dp]
+    lib.orc_affine_frame.restype = None
+    lib.orc_affine_frame.argtypes = [_i64, _i64] + [ctypes.c_double] * 4 + [_dp,
+                                                                            ctypes.POINTER(_i64)]
+    lib.orc_affine.restype = None
+    lib.orc_affine.argtypes = [ctypes.c_void_p, ctypes.c_int, _i64, _i64, _i64] + \
+        [ctypes.c_double] * 5 + [_i64, _fp, _dp]
     _lib = lib
     return lib
 
@@ -212,3 +221,37 @@ def view(stack, theta_deg, angle_deg, step_um, pixel_um, width_out=None):
     return {"shear": s, "warp": wf, "origin": b, "proj_width": w_in,
             "width": int(width_out),
             "psum": warp(d["psum"], wf, width_out), "pmax": warp(d["pmax"], wf, width_out)}
+
+
+def affine_frame(n_planes, cols, angle_deg, step_um, pixel_um, dy_um):
+    """(Y0, ny) of the real-space grid: smallest scan coordinate of the
+    stack's corners and the number of Y steps of ``dy_um`` covering it."""
+    y0, ny = ctypes.c_double(), _i64()
+    _load().orc_affine_frame(int(n_planes), int(cols), float(angle_deg), float(step_um),
+                             float(pixel_um), float(dy_um), ctypes.byref(y0), ctypes.byref(ny))
+    return y0.value, int(ny.value)
+
+
+def affine(stack, angle_deg, step_um, pixel_um, dy_um, y0=None, ny=None, vol64=False):
+    """Real-space deskew: vol[y][x][z] is the linear interpolation between
+    images floor(u) and floor(u)+1 at raw column z, row x, with
+    u = (Y0 + y dy - z p cos(alpha)) / z_step.  Returns float32 (or float64)
+    [ny][rows][cols] and (Y0, ny)."""
+    s = np.ascontiguousarray(stack)
+    if s.dtype == np.uint16:
+        is_f32 = 0
+    elif s.dtype == np.float32:
+        is_f32 = 1
+    else:
+        raise TypeError("oracle affine takes uint16 or float32 stacks")
+    n, r, c = s.shape
+    if y0 is None or ny is None:
+        y0_, ny_ = affine_frame(n, c, angle_deg, step_um, pixel_um, dy_um)
+        y0 = y0_ if y0 is None else y0
+        ny = ny_ if ny is None else ny
+    out32 = None if vol64 else np.empty((ny, r, c), np.float32)
+    out64 = np.empty((ny, r, c), np.float64) if vol64 else None
+    _load().orc_affine(s.ctypes.data_as(ctypes.c_void_p), is_f32, n, r, c, float(angle_deg),
+                       float(step_um), float(pixel_um), float(dy_um), float(y0), int(ny),
+                       _ptr(out32, _fp), _ptr(out64, _dp))
+    return (out64 if vol64 else out32), (float(y0), int(ny))

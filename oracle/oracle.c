@@ -252,3 +252,74 @@ void orc_warp(const double *proj, int64_t rows, int64_t width_in,
         }
     }
 }
+
+/* Real-space (affine) deskew, the alternative to the remap that the paper
+ * contrasts it with ("Physical principles", remap paragraph: an affine
+ * transformation of the whole stack, possible only once the stack is
+ * complete).  The stack is resampled onto a Cartesian grid of the sample:
+ *   X = r p            (rows are already lateral sample coordinates),
+ *   Z = c p sin(alpha)  (height above the coverslip of raw column c),
+ *   Y = Y0 + y dy       (scan axis, step dy chosen by the caller),
+ * where raw image n, column c images the scan coordinate
+ * Y = n z + c p cos(alpha) (the sheet is tilted by alpha from the scan axis).
+ * With Z on the raw column grid, every output voxel (y, x, z) lies on the
+ * line of raw column z between two images: its image coordinate is
+ *   u = (Y0 + y dy - z p cos(alpha)) / z_step
+ * and the value is the linear interpolation between images floor(u) and
+ * floor(u) + 1 (zero outside the stack).  Y0 is the smallest scan
+ * coordinate of the stack's corners and ny covers the largest.
+ * Output vol [ny][rows][cols]. */
+void orc_affine_frame(int64_t n_planes, int64_t cols, double angle_deg,
+                      double step_um, double pixel_um, double dy_um,
+                      double *y0, int64_t *ny)
+{
+    double alpha = angle_deg * ORC_PI / 180.0;
+    double pc = pixel_um * cos(alpha);
+    double lo = 0.0, hi = 0.0;
+    double corners[4] = {0.0, (double)(n_planes - 1) * step_um,
+                         (double)(cols - 1) * pc,
+                         (double)(n_planes - 1) * step_um + (double)(cols - 1) * pc};
+    for (int k = 0; k < 4; ++k) {
+        if (k == 0 || corners[k] < lo) lo = corners[k];
+        if (k == 0 || corners[k] > hi) hi = corners[k];
+    }
+    *y0 = lo;
+    *ny = (int64_t)floor((hi - lo) / dy_um) + 1;
+}
+
+void orc_affine(const void *stack, int is_f32, int64_t n_planes, int64_t rows,
+                int64_t cols, double angle_deg, double step_um,
+                double pixel_um, double dy_um, double y0, int64_t ny,
+                float *vol, double *vol64)
+{
+    double alpha = angle_deg * ORC_PI / 180.0;
+    double pc = pixel_um * cos(alpha);
+    const size_t esz = is_f32 ? sizeof(float) : sizeof(uint16_t);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t y = 0; y < ny; ++y) {
+        double yy = y0 + (double)y * dy_um;
+        for (int64_t x = 0; x < rows; ++x) {
+            for (int64_t z = 0; z < cols; ++z) {
+                double u = (yy - (double)z * pc) / step_um;
+                double fi = floor(u);
+                double f = u - fi;
+                int64_t n0 = (int64_t)fi;
+                double a = 0.0, b = 0.0;
+                if (n0 >= 0 && n0 < n_planes) {
+                    const char *row = (const char *)stack +
+                                      (size_t)((n0 * rows + x) * cols) * esz;
+                    a = raw_at(row, is_f32, cols, z);
+                }
+                if (n0 + 1 >= 0 && n0 + 1 < n_planes) {
+                    const char *row = (const char *)stack +
+                                      (size_t)(((n0 + 1) * rows + x) * cols) * esz;
+                    b = raw_at(row, is_f32, cols, z);
+                }
+                double d = (1.0 - f) * a + f * b;
+                size_t o = (size_t)((y * rows + x) * cols + z);
+                if (vol) vol[o] = (float)d;
+                if (vol64) vol64[o] = d;
+            }
+        }
+    }
+}
