@@ -206,6 +206,21 @@ def bench_view(torch, dsk, synth):
     return res
 
 
+def bench_affine(torch, dsk, synth):
+    """Real-space (affine) deskew of the 512 x 512 x 2048 stack onto a
+    0.115 um scan grid (3455 x 512 x 2048 float32 output)."""
+    st = synth.blob_stack((N, R, C), BLOBS, SEED, device="cuda")
+    y0, ny = dsk.affine_plan((N, R, C), ANGLE, STEP, PIXEL, PIXEL)
+    out = torch.empty((ny, R, C), dtype=torch.float32, device="cuda")
+    ms = _median_ms(torch, lambda: dsk.affine(st, ANGLE, STEP, PIXEL, PIXEL, out=out), 5)
+    alg = 2 * N * R * C + 4 * ny * R * C
+    del st, out
+    torch.cuda.empty_cache()
+    return {"workload": "affine deskew of the 512x512x2048 uint16 stack, 35 deg, dy 0.115 um",
+            "ny": ny, "ms": ms, "gbs": alg / ms / 1e6, "algorithmic_bytes": alg,
+            "voxels_per_s": ny * R * C / ms * 1e3}
+
+
 def bench_serving(torch, dsk, synth, n_req, rate):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time."""
@@ -243,9 +258,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,view,serving",
-                    help="comma list of extra measurements (batch, autograd, view, serving) "
-                         "or none")
+    ap.add_argument("--extras", default="batch,autograd,view,affine,serving",
+                    help="comma list of extra measurements (batch, autograd, view, affine, "
+                         "serving) or none")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
@@ -332,6 +347,10 @@ def main():
     if "view" in extras:
         log("view: shear-warp rotated views")
         ext["view"] = bench_view(torch, dsk, synth)
+    if "affine" in extras:
+        log("affine: real-space deskew")
+        ext["affine"] = bench_affine(torch, dsk, synth)
+        log(f"affine: {ext['affine']['ms']:.3f} ms, {ext['affine']['gbs']:.0f} GB/s")
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)

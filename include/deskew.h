@@ -303,6 +303,30 @@ int dsk_stretch_f32(const float *proj, int64_t rows, int64_t width_in,
                     double stretch, float *out, int64_t width_out,
                     hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * Real-space (affine) deskew ("Physical principles", remap paragraph: the
+ * affine transformation of the whole stack that the remap is contrasted
+ * with).  The stack is resampled onto a Cartesian grid of the sample:
+ * X = x p (rows), Z = z p sin(alpha) (raw columns), Y = Y0 + y dy (scan
+ * axis, step dy chosen by the caller).  Raw image n, column z images the
+ * scan coordinate n * step + z p cos(alpha), so voxel (y, x, z) lies on raw
+ * column z between images floor(u) and floor(u) + 1 with
+ *     u = (Y0 + y dy - z p cos(alpha)) / step
+ * and is their linear interpolation, zero outside the stack.  Output vol
+ * [ny][rows][cols] float32.
+ * ------------------------------------------------------------------- */
+
+/* Host-only grid of the stack: Y0 = the smallest scan coordinate of the
+ * stack's corners, ny = floor((largest - Y0) / dy) + 1.  DSK_EINVAL for a
+ * zero step or dy <= 0. */
+int dsk_affine_plan(dsk_dims d, dsk_geom g, double dy_um, double *y0_um,
+                    int64_t *ny);
+
+/* Resample a uint16 stack (DEVICE) into vol (DEVICE, [ny][rows][cols]
+ * float32) on the grid (y0_um, dy_um, ny), e.g. from dsk_affine_plan. */
+int dsk_affine_u16(const uint16_t *in, dsk_dims d, dsk_geom g, double dy_um,
+                   double y0_um, int64_t ny, float *vol, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

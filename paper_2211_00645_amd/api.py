@@ -314,3 +314,36 @@ def deskew_channels(frames, col0s, cols, angle_deg, step_um, pixel_um, *, vol=Tr
                 if key in res:
                     res[key].record_stream(cur)
     return out
+
+
+def affine_plan(shape, angle_deg, step_um, pixel_um, dy_um=None):
+    """(Y0, ny) of the real-space grid with scan step ``dy_um`` (default: the
+    pixel size)."""
+    dy = float(pixel_um if dy_um is None else dy_um)
+    y0, ny = ctypes.c_double(), ctypes.c_int64()
+    st = L.lib().dsk_affine_plan(_dims(shape), L.Geom(angle_deg, step_um, pixel_um), dy,
+                                 ctypes.byref(y0), ctypes.byref(ny))
+    L.check(st, "dsk_affine_plan")
+    return y0.value, int(ny.value)
+
+
+def affine(stack, angle_deg, step_um, pixel_um, dy_um=None, *, y0=None, ny=None, out=None,
+           stream=None):
+    """Real-space (affine) deskew of a uint16 CUDA stack: float32
+    [ny][rows][cols] on the Cartesian grid Y = Y0 + y dy, X = row,
+    Z = column p sin(alpha).  Returns (vol, (Y0, ny))."""
+    _check_stack(stack, (torch.uint16,))
+    dy = float(pixel_um if dy_um is None else dy_um)
+    y0_, ny_ = affine_plan(tuple(stack.shape), angle_deg, step_um, pixel_um, dy)
+    y0 = y0_ if y0 is None else float(y0)
+    ny = ny_ if ny is None else int(ny)
+    n, r, c = (int(v) for v in stack.shape)
+    if out is None:
+        out = torch.empty((ny, r, c), dtype=torch.float32, device=stack.device)
+    elif tuple(out.shape) != (ny, r, c) or out.dtype != torch.float32 or not out.is_contiguous():
+        raise ValueError(f"out must be contiguous float32 {(ny, r, c)}")
+    st = L.lib().dsk_affine_u16(_vp(stack), _dims(stack.shape),
+                                L.Geom(angle_deg, step_um, pixel_um), dy, y0, ny, _vp(out),
+                                _stream(stream))
+    L.check(st, "dsk_affine_u16")
+    return out, (y0, ny)

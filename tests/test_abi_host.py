@@ -161,3 +161,26 @@ def test_channel_entry_point_rejects_ranges_outside_the_frame():
     assert lib.dsk_deskew_channel_u16(fake, 16, -1, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
     assert lib.dsk_deskew_channel_u16(fake, 7, 0, d, g, fake, None, None, 0, None) == L.DSK_EINVAL
     assert lib.dsk_deskew_channel_u16(fake, 16, 8, d, g, None, None, None, 0, None) == L.DSK_EINVAL
+
+
+def test_affine_plan_matches_the_oracle_frame_and_rejects_bad_grids():
+    import oracle
+    for shape, ang, step, pix, dy in [((512, 512, 2048), 35.0, 0.4, 0.115, 0.115),
+                                      ((10, 3, 50), 30.0, -0.3, 0.1, 0.05),
+                                      ((1, 4, 7), 45.0, 0.2, 0.1, 0.3)]:
+        assert api.affine_plan(shape, ang, step, pix, dy) == \
+            oracle.affine_frame(shape[0], shape[2], ang, step, pix, dy)
+    lib = L.lib()
+    y0, ny = ctypes.c_double(), ctypes.c_int64()
+    d = L.Dims(4, 2, 8)
+    assert lib.dsk_affine_plan(d, L.Geom(30.0, 0.0, 0.1), 0.1, ctypes.byref(y0),
+                               ctypes.byref(ny)) == L.DSK_EINVAL
+    assert lib.dsk_affine_plan(d, L.Geom(30.0, 0.4, 0.1), 0.0, ctypes.byref(y0),
+                               ctypes.byref(ny)) == L.DSK_EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.dsk_affine_u16(None, d, L.Geom(30.0, 0.4, 0.1), 0.1, 0.0, 5, fake,
+                              None) == L.DSK_EINVAL
+    assert lib.dsk_affine_u16(fake, d, L.Geom(30.0, 0.4, 0.1), 0.1, 0.0, 0, fake,
+                              None) == L.DSK_EINVAL
+    assert lib.dsk_affine_u16(fake, d, L.Geom(30.0, 0.4, 0.1), 0.1, float("nan"), 5, fake,
+                              None) == L.DSK_EINVAL
