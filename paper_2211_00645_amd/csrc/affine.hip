@@ -7,14 +7,12 @@
 // floor(u) and floor(u) + 1, u = (Y - z p cos(a)) / s_z, and is their linear
 // interpolation (zero outside the stack).
 //
-// The output is several times the remap's volume, so the kernel is a
-// one-shot grid in output order: consecutive workgroups write consecutive
-// memory (the write stream stays on one front), each lane writes 4
-// consecutive z with one 16-byte store, and the interpolation reads come
-// from the two or three images the lane's 4 columns cross.  Consecutive y
-// of one (x, z range) re-read nearly the same input lines; they are
-// R*C/1024 workgroups apart (1024 for a 512 x 2048 image: a multiple of the
-// 8 XCDs, so the same XCD), and those reads hit its L2 or the MALL.
+// The output is several times the remap's volume and each output row
+// crosses many images, so a plain gather would fetch a cache line per pixel.
+// The main kernel (k_affine_ring) keeps the images a 64-column strip needs
+// in an LDS ring while it sweeps y; the one-shot kernel (k_affine, one lane
+// per 4 output columns in output order) covers the geometries the ring does
+// not (the band moving a whole image or more per y, or wider than the ring).
 #include <cmath>
 #include <cstdint>
 
@@ -88,6 +86,177 @@ __global__ __launch_bounds__(kAffBlock) void k_affine(AffArgs<TIn> a) {
     }
 }
 
+// Ring kernel: one wavefront per (y chunk, row x, 64 columns), sweeping its
+// y chunk in the direction in which u grows.  The images the 64 columns
+// need at one y form a band of about 64 |uz| + 2 consecutive images, moving
+// by |uy| < 1 images per y.  The band lives in an LDS ring of 32 image rows
+// (64 floats each, row n mod 32); each image row enters once, with one
+// coalesced 128-byte load issued a few steps before its first use and
+// written to the ring when it is consumed.  Every voxel then reads its two
+// images from LDS instead of gathering them from L2.
+constexpr int kAffAhead = 8;
+
+template <typename TIn>
+struct RingArgs {
+    AffArgs<TIn> a;
+    int64_t ychunk;       // y values per wavefront
+    int32_t ztiles;       // 64-column tiles per row
+};
+
+// YQ y values per step (1, or 4 when the band moves less than half an
+// image per y, i.e. at most 2 new images per step); AHEAD steps of
+// look-ahead.  The ring has 32 rows plus a copy of row 0 after row 31, so
+// the two images a voxel needs are always in consecutive rows.  The host
+// keeps every u within +-1e9, so floors fit an int.
+template <typename TIn, int YQ, int AHEAD>
+__global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
+    constexpr int NF = YQ == 1 ? 1 : 2;        // fetches per step
+    __shared__ float ring[33 * 64];
+    const AffArgs<TIn> &a = ra.a;
+    const int lane = (int)threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int64_t per_chunk = (int64_t)a.R * ra.ztiles;
+    const int64_t yc = b / per_chunk;
+    const int64_t rem = b - yc * per_chunk;
+    const int x = (int)(rem / ra.ztiles);
+    const int zb = 64 * (int)(rem - (int64_t)x * ra.ztiles);
+    const int ze = zb + 63 < a.C ? zb + 63 : a.C - 1;
+    const bool zok = zb + lane < a.C;
+    const int zc = zok ? zb + lane : ze;       // the column this lane reads and writes
+    const int64_t y_lo = yc * ra.ychunk;
+    const int64_t y_hi = (y_lo + ra.ychunk < a.ny ? y_lo + ra.ychunk : a.ny);
+    const int ny_c = (int)(y_hi - y_lo);
+    const int steps = (ny_c + YQ - 1) / YQ;
+    // y runs in the direction in which u grows; u = P(y) - z uz, where the
+    // chain P(next y) = P(y) + |uy| gives the one value both the band
+    // bookkeeping and the voxels use, so they always agree on which images
+    // are needed
+    const bool up = a.uy > 0.0;
+    const int64_t y_first = up ? y_lo : y_hi - 1;
+    const double ds = fabs(a.uy);
+    const double uzl = __dmul_rn((double)zc, a.uz);
+    const double uzb = __dmul_rn((double)zb, a.uz), uze = __dmul_rn((double)ze, a.uz);
+    const double uz_min = uzb < uze ? uzb : uze, uz_max = uzb < uze ? uze : uzb;
+    auto fl = [](double v) { return (int)floor(v); };
+    // P of the first y of each of the next AHEAD steps, and of step AHEAD
+    double Pq[AHEAD];
+    Pq[0] = __dadd_rn(a.u0, __dmul_rn((double)y_first, a.uy));
+#pragma unroll
+    for (int k = 1; k < AHEAD; ++k) {
+        double p = Pq[k - 1];
+#pragma unroll
+        for (int i = 0; i < YQ; ++i) p = __dadd_rn(p, ds);
+        Pq[k] = p;
+    }
+    double Pa = Pq[AHEAD - 1];
+#pragma unroll
+    for (int i = 0; i < YQ; ++i) Pa = __dadd_rn(Pa, ds);
+    // last P of a step whose first P is p
+    auto last_p = [&](double p) {
+#pragma unroll
+        for (int i = 1; i < YQ; ++i) p = __dadd_rn(p, ds);
+        return p;
+    };
+    // images outside the stack read image 0 or N-1 and enter the ring
+    // scaled by 0, so every fetch is one unconditional coalesced load and
+    // the ring holds zeros for them
+    const TIn *rowx = a.in + (int64_t)x * a.C;    // wave-uniform base
+    const int64_t plane = (int64_t)a.R * a.C;
+    auto load = [&](int n) {
+        const TIn *base = rowx + (int64_t)(n < 0 ? 0 : (n >= a.N ? a.N - 1 : n)) * plane;
+        return base[zc];
+    };
+    auto scale = [&](int n) { return (n >= 0 && n < a.N) ? 1.0f : 0.0f; };
+    auto put = [&](int m, float v) {
+        const int r = m & 31;
+        ring[r * 64 + lane] = v;
+        if (r == 0) ring[32 * 64 + lane] = v;
+    };
+    // fill: the band of the first AHEAD steps, 8 loads at a time
+    int have;
+    {
+        const int lo0 = fl(__dsub_rn(Pq[0], uz_max));
+        const int last = steps - 1 < AHEAD - 1 ? steps - 1 : AHEAD - 1;
+        const int top = fl(__dsub_rn(last_p(Pq[last]), uz_min)) + 1;
+        for (int n = lo0; n <= top; n += 8) {
+            TIn t[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) t[i] = load(n + i <= top ? n + i : top);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int m = n + i <= top ? n + i : top;
+                put(m, (float)t[i] * scale(m));
+            }
+        }
+        have = top;
+    }
+    // per step exactly NF fetches and YQ stores: the images the step AHEAD
+    // later first needs, or again the newest image (its ring row is
+    // rewritten with the same values)
+    TIn q[AHEAD][NF];
+    int qn[AHEAD][NF];
+#pragma unroll
+    for (int k = 0; k < AHEAD; ++k)
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            q[k][i] = 0;
+            qn[k][i] = have;
+        }
+    const int64_t ostep = (up ? 1 : -1) * (int64_t)a.R * a.C;
+    float *orow = a.vol + (y_first * a.R + x) * (int64_t)a.C;   // wave-uniform
+
+    auto step = [&](int k, int j, bool tail) {
+        // the images fetched AHEAD steps ago enter the ring
+        if (j >= AHEAD) {
+#pragma unroll
+            for (int i = 0; i < NF; ++i) put(qn[k][i], (float)q[k][i] * scale(qn[k][i]));
+        }
+        const double p0 = Pq[k];                // P of this step's first y
+        int m = have;
+        if (j + AHEAD < steps) {
+            const int h = fl(__dsub_rn(last_p(Pa), uz_min)) + 1;  // leading edge
+            m = h > have ? h : have;
+        }
+        Pq[k] = Pa;
+#pragma unroll
+        for (int i = 0; i < YQ; ++i) Pa = __dadd_rn(Pa, ds);
+        // at most NF new images: have + 1 .. m
+#pragma unroll
+        for (int i = 0; i < NF; ++i) {
+            const int mi = have + 1 + i <= m ? have + 1 + i : m;
+            q[k][i] = load(mi);
+            qn[k][i] = mi;
+        }
+        have = m;
+        double p = p0;
+#pragma unroll
+        for (int i = 0; i < YQ; ++i) {
+            if (i) p = __dadd_rn(p, ds);
+            const double u = __dsub_rn(p, uzl);
+            const double fi = floor(u);
+            const int r = (int)fi & 31;
+            const double f = __dsub_rn(u, fi);
+            // both weights rounded once from FP64 (1 - wlo in FP32 would lose
+            // the relative precision of a small 1 - f)
+            const float wlo = (float)f, whi = (float)__dsub_rn(1.0, f);
+            const float lo = ring[r * 64 + lane];
+            const float hi = ring[r * 64 + 64 + lane];
+            // lanes past the last column repeat the last column's value to
+            // its address: one unconditional store per y
+            if (!tail || j * YQ + i < ny_c) store_f32<true>(orow + zc, fmaf(wlo, hi, whi * lo));
+            orow += ostep;
+        }
+    };
+    const int full = (ny_c / YQ) / AHEAD * AHEAD;   // steps with all YQ y values, whole groups
+    for (int j0 = 0; j0 < full; j0 += AHEAD) {
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) step(k, j0 + k, false);
+    }
+#pragma unroll
+    for (int k = 0; k < AHEAD; ++k)
+        if (full + k < steps) step(k, full + k, true);
+}
+
 bool geom_ok(dsk_geom g) {
     return std::isfinite(g.angle_deg) && std::isfinite(g.step_um) && std::isfinite(g.pixel_um) &&
            g.pixel_um > 0.0 && g.step_um != 0.0;
@@ -126,6 +295,34 @@ extern "C" int dsk_affine_u16(const uint16_t *in, dsk_dims d, dsk_geom g, double
     const int64_t threads = ny * (int64_t)d.rows * a.zgroups;
     if (threads / kAffBlock >= kMaxI32) return DSK_ESHAPE;
     const dim3 grid((unsigned)((threads + kAffBlock - 1) / kAffBlock));
+    // ring kernels when the band moves less than one image per y and fits
+    // 32 ring rows; otherwise the one-shot kernel
+    // y values per wavefront: long sweeps amortise the ring fill (measured
+    // on 512x512x2048: 32 -> 5.08 ms, 128 -> 4.56 ms, 512 -> 4.43 ms)
+    const int64_t ychunk = 512;
+    const int32_t ztiles = (d.cols + 63) / 64;
+    const int64_t chunks = (ny + ychunk - 1) / ychunk;
+    const int64_t blocks = ychunk > 0 ? chunks * d.rows * ztiles : kMaxI32;
+    const double band4 = 63.0 * std::fabs(a.uz) + (4 * 4 + 4) * std::fabs(a.uy) + 4.0;
+    const double band1 = 63.0 * std::fabs(a.uz) + (kAffAhead + 1) * std::fabs(a.uy) + 4.0;
+    // the ring kernels take floors of u as ints: every u of the grid
+    // (u0 + y uy - z uz over the whole output) must stay within +-1e9
+    const double ue[4] = {a.u0, a.u0 + (double)(ny - 1) * a.uy, a.u0 - (double)(d.cols - 1) * a.uz,
+                          a.u0 + (double)(ny - 1) * a.uy - (double)(d.cols - 1) * a.uz};
+    bool u_ok = true;
+    for (double v : ue) u_ok = u_ok && std::fabs(v) < 1.0e9;
+    if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.499 && band4 <= 32.0) {
+        const RingArgs<uint16_t> ra{a, ychunk, ztiles};
+        hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4>), dim3((unsigned)blocks), dim3(64), 0,
+                           stream, ra);
+        return hip_status(hipGetLastError());
+    }
+    if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.999 && band1 <= 32.0) {
+        const RingArgs<uint16_t> ra{a, ychunk, ztiles};
+        hipLaunchKernelGGL((k_affine_ring<uint16_t, 1, kAffAhead>), dim3((unsigned)blocks),
+                           dim3(64), 0, stream, ra);
+        return hip_status(hipGetLastError());
+    }
     const bool vec = d.cols % 4 == 0 && ((uintptr_t)vol & 15) == 0;
     if (vec)
         hipLaunchKernelGGL((k_affine<uint16_t, true>), grid, dim3(kAffBlock), 0, stream, a);
