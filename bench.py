@@ -221,6 +221,34 @@ def bench_affine(torch, dsk, synth):
             "voxels_per_s": ny * R * C / ms * 1e3}
 
 
+def bench_rolling(torch, dsk, synth):
+    """Rolling display mode: time per image update (remap of one image,
+    max-tree path, running sum, projections), at the paper's live region
+    (50 images of 1304 x 87 px spread over 3652 px) and at the benchmark
+    stack's shape (512 images of 512 x 2048)."""
+    from paper_2211_00645_amd.rolling import RollingView
+    res = {"workload": "rolling update, one image per call"}
+    for name, (n, r, c), kw in (("paper_1304x87x50", (50, 1304, 87),
+                                 {"shift_px": (3652 - 87) / 49}),
+                                ("stack_512x512x2048", (N, R, C),
+                                 {"angle_deg": ANGLE, "step_um": STEP, "pixel_um": PIXEL})):
+        st = synth.blob_stack((n, r, c), 50, 21, device="cuda")
+        rv = RollingView(n, r, c, **kw)
+        for i in range(n):
+            rv.update(i, st[i])
+        torch.cuda.synchronize()
+        k = [0]
+
+        def one():
+            rv.update(k[0] % n, st[k[0] % n])
+            k[0] += 1
+        ms = _median_ms(torch, one, 50)
+        res[name] = {"ms_per_image": ms, "images_per_s": 1e3 / ms, "width": rv.width}
+        del rv, st
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(torch, dsk, synth, n_req, rate):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time."""
@@ -258,9 +286,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,view,affine,serving",
+    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,serving",
                     help="comma list of extra measurements (batch, autograd, view, affine, "
-                         "serving) or none")
+                         "rolling, serving) or none")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
@@ -351,6 +379,9 @@ def main():
         log("affine: real-space deskew")
         ext["affine"] = bench_affine(torch, dsk, synth)
         log(f"affine: {ext['affine']['ms']:.3f} ms, {ext['affine']['gbs']:.0f} GB/s")
+    if "rolling" in extras:
+        log("rolling: per-image update")
+        ext["rolling"] = bench_rolling(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)

@@ -75,9 +75,9 @@ typedef struct {
  * as fit); pace_gbs: plane pacing of the vector kernel -- a wavefront that
  * runs ahead of the schedule "the launch's resident wavefronts move this
  * many GB/s" sleeps briefly, which keeps the wavefronts on neighbouring
- * planes and the write stream local (0 = no pacing; pacing only delays,
- * it never waits on another wavefront).  Every shape gives bitwise
- * identical results. */
+ * planes and the write stream local (0 = no pacing; launches without a
+ * volume are not paced; pacing only delays, it never waits on another
+ * wavefront).  Every shape gives bitwise identical results. */
 typedef struct {
     int32_t block, per_thread, nt_store, unroll, wg_per_cu, pace_gbs;
 } dsk_tune;

@@ -106,7 +106,8 @@ void set_pacing(JobDev *tab, int n, const dsk_tune &t, int grid) {
         const double blocks = (double)r.tiles_x * r.R + r.edge_blocks;
         const double plane_bytes =
             2.0 * (double)r.R * r.C + (r.vol ? 4.0 * (double)r.R * (double)r.W : 0.0);
-        r.tau256 = r.vec ? pace_tau256(plane_bytes, (double)grid / blocks, t.pace_gbs) : 0u;
+        r.tau256 = (r.vec && r.vol) ? pace_tau256(plane_bytes, (double)grid / blocks, t.pace_gbs)
+                                    : 0u;
     }
 }
 

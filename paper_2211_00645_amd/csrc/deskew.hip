@@ -100,8 +100,10 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
         if (vec) {
             auto kern = k_forward_vec<TIn, B, PT / 4, U, NT>;
             const int64_t blocks = tiles * a.R + edge;
-            if (pace_gbs > 0) {
-                // one workgroup's share of a plane's bytes, timed at pace_gbs
+            if (pace_gbs > 0 && a.vol) {
+                // pacing keeps the volume's write stream local; a launch
+                // without a volume only reads and is not paced.  One
+                // workgroup's share of a plane's bytes, timed at pace_gbs
                 const double plane_bytes = (double)a.R * a.C * sizeof(TIn) +
                                            (a.vol ? 4.0 * (double)a.R * (double)a.W : 0.0);
                 const double t = plane_bytes / (double)blocks / ((double)pace_gbs * 1e9) * 1e8 *
