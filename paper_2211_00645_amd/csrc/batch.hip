@@ -98,16 +98,20 @@ int persistent_grid(const dsk_tune &t, int64_t total_tiles) {
     return (int)g;
 }
 
-// Plane pacing of each job: the grid's resident workgroups sweep a job's
-// tiles together, so the share of the job running at once is grid / tiles.
+// Plane pacing of each job: every resident workgroup of the persistent grid
+// gets a fair share of the pace, whatever job its current tile belongs to,
+// so a tile of job j moves one plane in (job j's plane bytes / its tiles)
+// x grid / pace.  Jobs without a volume only read and are not paced.
 void set_pacing(JobDev *tab, int n, const dsk_tune &t, int grid) {
     for (int i = 0; i < n; ++i) {
         JobDev &r = tab[i];
+        r.tau256 = 0;
+        if (!r.vec || !r.vol || t.pace_gbs <= 0) continue;
         const double blocks = (double)r.tiles_x * r.R + r.edge_blocks;
-        const double plane_bytes =
-            2.0 * (double)r.R * r.C + (r.vol ? 4.0 * (double)r.R * (double)r.W : 0.0);
-        r.tau256 = (r.vec && r.vol) ? pace_tau256(plane_bytes, (double)grid / blocks, t.pace_gbs)
-                                    : 0u;
+        const double plane_bytes = 2.0 * (double)r.R * r.C + 4.0 * (double)r.R * (double)r.W;
+        const double tau = plane_bytes / blocks * (double)grid / ((double)t.pace_gbs * 1e9) *
+                           1e8 * 256.0;
+        r.tau256 = tau >= 4.0e9 ? 4000000000u : (uint32_t)tau;
     }
 }
 
@@ -207,9 +211,8 @@ void cache_store(const char *path, const std::string &key, const dsk_tune &t, do
 // Launch shapes the autotuner times.
 std::vector<dsk_tune> candidates() {
     std::vector<dsk_tune> c;
-    for (int b : {64, 128})
-        for (int u : {1, 2, 4})
-            for (int pace : {0, 5000, 5500}) c.push_back(dsk_tune{b, 4, 1, u, 0, pace});
+    for (int u : {1, 2, 4})
+        for (int pace : {0, 5500}) c.push_back(dsk_tune{64, 4, 1, u, 0, pace});
     c.push_back(dsk_tune{256, 8, 1, 2, 0, 0});
     return c;
 }
