@@ -14,11 +14,12 @@ constexpr int64_t kMaxI32 = 2147483647;
 
 // Default forward launch shape: 64-thread workgroups, one 4-column group per
 // lane, non-temporal stores, 2-plane pipeline (built for 8 waves per SIMD),
-// paced at 5800 GB/s.  On the 512x512x2048 stack the pace holds up to
-// about 5900 GB/s (0.847 ms); above that the wavefronts fall behind the
-// schedule, stop sleeping and drift apart (0.92-0.95 ms); 5800 gives 0.859
-// ms with a small margin.
-constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5800};
+// paced at 5700 GB/s.  On the 512x512x2048 stack, back to back, the pace
+// holds up to about 5850 GB/s (5800: 0.851 ms); faster than that the
+// wavefronts fall behind the schedule, stop sleeping and drift apart
+// (0.83-0.95 ms, erratic), and boxes differ by a few percent, so the
+// default keeps a margin (5700: 0.862 ms, every launch within 1%).
+constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
 
 inline bool dims_ok(dsk_dims d) {
     return d.planes > 0 && d.rows > 0 && d.cols > 0;
