@@ -362,41 +362,52 @@ class GPUExecutor:
             if self.buf is None:
                 self.buf = torch.empty((self.arena.size,), dtype=torch.uint8, device=self.device)
             base = self.arena.alloc(total)        # raises NoSpace when fragmented
-        proj = sum(2 * rows * w for (_, _, _, rows, w) in items)
-        st = self.staging[slot]
-        if st is None or st.numel() < proj:
-            st = torch.empty((max(proj, 1 << 20),), dtype=torch.float32, pin_memory=True)
-            self.staging[slot] = st
-        jobs, outs, host = [], [], []
-        off = 0
-        hoff = 0
-        with torch.cuda.stream(s):
-            for (r, ch, n, rows, w) in items:
-                stack = self.pool[(r.rows, r.cols, ch)][:r.planes]
-                out = None
-                if base is not None:
-                    out = {"psum": self._view(base, off, (rows, w)),
-                           "pmax": self._view(base, off + 4 * rows * w, (rows, w))}
-                    nb = 8 * rows * w
-                    if self.keep_volume:
-                        out["vol"] = self._view(base, off + nb, (n, rows, w))
-                        nb += 4 * n * rows * w
-                    off += self.arena.round(nb)
-                job, res = plan_job(stack, r.angle_deg, r.step_um, r.pixel_um,
-                                    vol=self.keep_volume, out=out)
-                jobs.append(job)
-                outs.append((r, ch, res))
-            self.launcher.launch(jobs, self.tune, stream=s)
-            for r, ch, res in outs:
-                m = res["psum"].numel()
-                hp = st[hoff: hoff + m].view(res["psum"].shape)
-                hm = st[hoff + m: hoff + 2 * m].view(res["pmax"].shape)
-                hoff += 2 * m
-                hp.copy_(res["psum"], non_blocking=True)
-                hm.copy_(res["pmax"], non_blocking=True)
-                host.append((hp, hm))
-            ev = torch.cuda.Event()
-            ev.record(s)
+        launched = False
+        try:
+            proj = sum(2 * rows * w for (_, _, _, rows, w) in items)
+            st = self.staging[slot]
+            if st is None or st.numel() < proj:
+                st = torch.empty((max(proj, 1 << 20),), dtype=torch.float32, pin_memory=True)
+                self.staging[slot] = st
+            jobs, outs, host = [], [], []
+            off = 0
+            hoff = 0
+            with torch.cuda.stream(s):
+                for (r, ch, n, rows, w) in items:
+                    stack = self.pool[(r.rows, r.cols, ch)][:r.planes]
+                    out = None
+                    if base is not None:
+                        out = {"psum": self._view(base, off, (rows, w)),
+                               "pmax": self._view(base, off + 4 * rows * w, (rows, w))}
+                        nb = 8 * rows * w
+                        if self.keep_volume:
+                            out["vol"] = self._view(base, off + nb, (n, rows, w))
+                            nb += 4 * n * rows * w
+                        off += self.arena.round(nb)
+                    job, res = plan_job(stack, r.angle_deg, r.step_um, r.pixel_um,
+                                        vol=self.keep_volume, out=out)
+                    jobs.append(job)
+                    outs.append((r, ch, res))
+                self.launcher.launch(jobs, self.tune, stream=s)
+                launched = True
+                for r, ch, res in outs:
+                    m = res["psum"].numel()
+                    hp = st[hoff: hoff + m].view(res["psum"].shape)
+                    hm = st[hoff + m: hoff + 2 * m].view(res["pmax"].shape)
+                    hoff += 2 * m
+                    hp.copy_(res["psum"], non_blocking=True)
+                    hm.copy_(res["pmax"], non_blocking=True)
+                    host.append((hp, hm))
+                ev = torch.cuda.Event()
+                ev.record(s)
+        except BaseException:
+            # give the outputs' arena block back; once the launch is queued,
+            # only after the stream has finished with it
+            if base is not None:
+                if launched:
+                    s.synchronize()
+                self.arena.free(base)
+            raise
         return (ev, outs, host, base)
 
     def done(self, tok):

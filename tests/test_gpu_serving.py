@@ -99,3 +99,18 @@ def test_arena_outputs_equal_solo_runs(pool):
             torch.cuda.synchronize()
             assert torch.equal(r.result[ch]["psum"], solo["psum"].cpu()), (r.rid, ch)
             assert torch.equal(r.result[ch]["pmax"], solo["pmax"].cpu()), (r.rid, ch)
+
+
+def test_failed_submit_returns_its_arena_block(pool):
+    """A request the executor cannot serve (no stack of its shape in the
+    pool) fails; its batch's arena block and budget are given back and the
+    requests after it are served."""
+    reqs = _trace(6, 2000.0, 4)
+    reqs[2].rows, reqs[2].cols = 96, 128            # not in the pool
+    ex = GPUExecutor(pool, n_slots=2, arena_bytes=1 << 30)
+    sch = Scheduler(ex, budget_bytes=1 << 30, n_slots=2, max_batch=1)
+    done = sch.run(reqs)
+    status = {r.rid: r.status for r in done}
+    assert status[2] == "failed"
+    assert all(st == "done" for rid, st in status.items() if rid != 2)
+    assert ex.arena.used == 0 and sch.used == 0
