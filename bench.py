@@ -249,6 +249,33 @@ def bench_rolling(torch, dsk, synth):
     return res
 
 
+def bench_scaling(torch, dsk, synth):
+    """Forward time against the number of images N (512 x 2048 images at
+    35 deg) and against the output width W (512 images, scan step varied):
+    the paper's processing time grows linearly in both (Supp. Table 1).
+    Each frame is timed with the library default and with the shape the
+    tuner picks for it."""
+    res = {"workload": "forward, 512x2048 uint16 images", "vs_planes": [], "vs_width": []}
+    st = synth.blob_stack((N, R, C), BLOBS, SEED, device="cuda")
+
+    def one(sub, step):
+        w, _ = dsk.plan(tuple(sub.shape), shift=dsk.shift_px(ANGLE, step, PIXEL))
+        tuned = dsk.autotune(sub, ANGLE, step, PIXEL, reps=6)["tune"]
+        ms_def = _median_ms(torch, lambda: dsk.deskew(sub, ANGLE, step, PIXEL), 10)
+        ms = _median_ms(torch, lambda: dsk.deskew(sub, ANGLE, step, PIXEL, tune=tuned), 10)
+        alg = algorithmic_bytes(sub.shape[0], R, C, w)
+        return {"width": w, "ms_default": ms_def, "ms_tuned": ms,
+                "gbs_tuned": alg / ms / 1e6, "tune": tuned}
+
+    for n in (64, 128, 256, 512):
+        res["vs_planes"].append(dict(planes=n, **one(st[:n], STEP)))
+    for step in (0.1, 0.2, 0.4, 0.8):
+        res["vs_width"].append(dict(step_um=step, **one(st, step)))
+    del st
+    torch.cuda.empty_cache()
+    return res
+
+
 def bench_serving(torch, dsk, synth, n_req, rate):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time."""
@@ -286,9 +313,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,serving",
+    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,scaling,serving",
                     help="comma list of extra measurements (batch, autograd, view, affine, "
-                         "rolling, serving) or none")
+                         "rolling, scaling, serving) or none")
+    ap.add_argument("--tune", default="auto",
+                    help="launch shape of the timed forward: auto (the library's tuner, run "
+                         "once before the warm-up) or default (the library default)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
     args = ap.parse_args()
@@ -318,8 +348,19 @@ def main():
             "psum": torch.empty((R, w), dtype=torch.float32, device=dev),
             "pmax": torch.empty((R, w), dtype=torch.float32, device=dev)}
 
+    if args.tune == "auto":
+        log("tuning the launch shape for this frame")
+        tuned = dsk.autotune(stack, ANGLE, STEP, PIXEL, out=outs, reps=8)
+        shape = tuned["tune"]
+        log(f"launch shape {shape} ({tuned['ms']:.4f} ms upper quartile)")
+    elif args.tune == "default":
+        shape = None
+    else:
+        print(f"--tune must be auto or default (got {args.tune})", file=sys.stderr)
+        sys.exit(2)
+
     def step():
-        return dsk.deskew(stack, ANGLE, STEP, PIXEL, out=outs)
+        return dsk.deskew(stack, ANGLE, STEP, PIXEL, out=outs, tune=shape)
 
     log(f"warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -382,6 +423,9 @@ def main():
     if "rolling" in extras:
         log("rolling: per-image update")
         ext["rolling"] = bench_rolling(torch, dsk, synth)
+    if "scaling" in extras:
+        log("scaling: time vs images and width")
+        ext["scaling"] = bench_scaling(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)
@@ -403,6 +447,7 @@ def main():
                                "0.4 um step, 0.115 um pixel",
                    "planes": N, "rows": R, "cols": C, "out_width": w, "origin": b,
                    "input": "u16", "volume": "f32", "sum_accumulation": "f64",
+                   "launch_shape": shape or "library default",
                    "parallelism": "single GPU"},
         "hbm_gbs": alg / (ms_per_step * 1e-3) / 1e9,
         "kernel_ms_avg": avg_kern_ms,

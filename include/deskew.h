@@ -146,6 +146,26 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
                              float *pmax, int64_t out_width,
                              const dsk_tune *tune, hipStream_t stream);
 
+/* Launch-shape tuner for one frame (the shape a live stream deskews over
+ * and over).  Times candidate shapes -- one or two 4-column groups per
+ * lane, unpaced and paced at 5000-6000 GB/s, and the default -- each `reps`
+ * times (3..64) round-robin after one untimed round, on the caller's own
+ * buffers and stream, and returns in *tune the shape with the lowest
+ * upper-quartile time (*ms, host, may be NULL).  Arguments as
+ * dsk_deskew_offsets_tuned.  Every trial computes the full result, so the
+ * outputs may be written (with the correct values) or, when the choice is
+ * already known, left untouched: call the forward with *tune afterwards.
+ * The choice is remembered per architecture, input type, dims, out_width,
+ * output set and offsets/uniform scan, in the process and, if the
+ * environment variable DSK_TUNE_CACHE names a file, in that JSON file; a
+ * remembered choice returns at once without launching.  Synchronises the
+ * stream while timing.  Errors of the arguments are those of the forward. */
+int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
+                        const double *offsets_dev, double shift_px,
+                        int64_t origin, float *vol, float *psum, float *pmax,
+                        int64_t out_width, int reps, hipStream_t stream,
+                        dsk_tune *tune, double *ms);
+
 /* Adjoint of the remap (its transpose) applied to grad_vol [planes][rows]
  * [out_width], written as a gather with no atomics:
  *   grad_in[n][r][c] = (1-phi) gD[n][r][c+k] + phi gD[n][r][c+k+1],

@@ -7,8 +7,8 @@ views, multi-channel frames and the real-space (affine) deskew -- runs in the HI
 ``libdeskew.so`` (C ABI in ``include/deskew.h``).  Import is light: the
 library is loaded on first use and its absence is an error, never a fallback.
 """
-from .api import (adjoint, affine, affine_plan, backward, deskew,  # noqa: F401
+from .api import (adjoint, affine, affine_plan, autotune, backward, deskew,  # noqa: F401
                   deskew_channels, plan, shear_grad, shift_px, stretch, view, view_plan)
 
-__all__ = ["deskew", "deskew_channels", "plan", "shift_px", "backward", "adjoint",
+__all__ = ["deskew", "autotune", "deskew_channels", "plan", "shift_px", "backward", "adjoint",
            "shear_grad", "view", "view_plan", "stretch", "affine", "affine_plan"]

@@ -59,6 +59,9 @@ _SIGS = {
     "dsk_deskew_offsets_tuned": (ctypes.c_int, [c_vp, ctypes.c_int, Dims, c_vp, c_dbl, c_i64,
                                                 c_vp, c_vp, c_vp, c_i64,
                                                 ctypes.POINTER(Tune), c_vp]),
+    "dsk_deskew_autotune": (ctypes.c_int, [c_vp, ctypes.c_int, Dims, c_vp, c_dbl, c_i64,
+                                           c_vp, c_vp, c_vp, c_i64, ctypes.c_int, c_vp,
+                                           ctypes.POINTER(Tune), ctypes.POINTER(c_dbl)]),
     "dsk_deskew_adjoint_f32": (ctypes.c_int, [c_vp, Dims, c_vp, c_i64, c_i64, c_vp, c_vp]),
     "dsk_shear_grad_workspace_bytes": (c_sz, [Dims]),
     "dsk_shear_grad_f32": (ctypes.c_int, [c_vp, c_vp, Dims, c_vp, c_i64, c_i64, c_vp, c_vp,

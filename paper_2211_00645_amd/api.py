@@ -83,17 +83,8 @@ def _offsets_dev(offsets, device):
     return o
 
 
-def deskew(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
-           offsets=None, origin=None, width=None, vol=True, psum=True, pmax=True,
-           out=None, tune=None, stream=None):
-    """Deskew ``stack`` and project it (one fused pass).
-
-    Geometry is either (angle_deg, step_um, pixel_um) for a uniform scan, or
-    explicit per-plane ``offsets`` in pixels.  ``origin``/``width`` default
-    to the full frame.  ``out`` may hold preallocated ``vol``/``psum``/
-    ``pmax`` tensors.  Returns a dict with the outputs, ``origin`` and
-    ``width``.
-    """
+def _setup(stack, angle_deg, step_um, pixel_um, offsets, origin, width, vol, psum, pmax, out):
+    """Geometry, frame and output tensors shared by deskew() and autotune()."""
     _check_stack(stack)
     dev = stack.device
     shape = tuple(stack.shape)
@@ -121,18 +112,71 @@ def deskew(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
         elif t.shape != shp or t.dtype != torch.float32 or not t.is_contiguous() or t.device != dev:
             raise ValueError(f"out[{key!r}] must be contiguous float32 {shp} on {dev}")
         res[key] = t
+    od = None if offsets is None else _offsets_dev(offsets, dev)
+    res["_offsets_dev"] = od          # keep alive until the kernel has read it
+    return shape, shift, w0, res
+
+
+def _autotune_call(stack, shape, shift, res, reps, s):
+    tn = L.Tune()
+    ms = ctypes.c_double()
+    st = L.lib().dsk_deskew_autotune(
+        _vp(stack), int(stack.dtype == torch.float32), _dims(shape), _vp(res["_offsets_dev"]),
+        float(shift or 0.0), res["origin"], _vp(res.get("vol")), _vp(res.get("psum")),
+        _vp(res.get("pmax")), res["width"], int(reps), s, ctypes.byref(tn), ctypes.byref(ms))
+    L.check(st, "dsk_deskew_autotune")
+    return tn, ms.value
+
+
+def autotune(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
+             offsets=None, origin=None, width=None, vol=True, psum=True, pmax=True,
+             out=None, reps=6, stream=None):
+    """Launch shape for deskewing stacks of this frame on this device.
+
+    Arguments as :func:`deskew`.  Times the library's candidate shapes
+    (pacing rate, columns per lane) on this stack and returns
+    ``{"tune": shape dict, "ms": upper-quartile time}``; the choice is
+    remembered per frame (and in the ``DSK_TUNE_CACHE`` file when that
+    variable is set), so later calls return at once.  Pass the shape as
+    ``deskew(..., tune=...)``, or call ``deskew(..., tune="auto")``.
+    """
+    shape, shift, _, res = _setup(stack, angle_deg, step_um, pixel_um, offsets, origin, width,
+                                  vol, psum, pmax, out)
+    tn, ms = _autotune_call(stack, shape, shift, res, reps, _stream(stream))
+    return {"tune": tn.as_dict(), "ms": ms}
+
+
+def deskew(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
+           offsets=None, origin=None, width=None, vol=True, psum=True, pmax=True,
+           out=None, tune=None, stream=None):
+    """Deskew ``stack`` and project it (one fused pass).
+
+    Geometry is either (angle_deg, step_um, pixel_um) for a uniform scan, or
+    explicit per-plane ``offsets`` in pixels.  ``origin``/``width`` default
+    to the full frame.  ``out`` may hold preallocated ``vol``/``psum``/
+    ``pmax`` tensors.  ``tune``: None (the library default), a launch-shape
+    dict, or ``"auto"`` (the shape :func:`autotune` picks for this frame,
+    measured on the first call).  Returns a dict with the outputs,
+    ``origin`` and ``width``.
+    """
+    shape, shift, w0, res = _setup(stack, angle_deg, step_um, pixel_um, offsets, origin, width,
+                                   vol, psum, pmax, out)
+    origin, width, od = res["origin"], res["width"], res["_offsets_dev"]
     v, ps, pm = res.get("vol"), res.get("psum"), res.get("pmax")
     lib = L.lib()
     s = _stream(stream)
-    tn = _tune(tune)
+    if isinstance(tune, str):
+        if tune != "auto":
+            raise ValueError("tune must be None, a shape dict or 'auto'")
+        tn = _autotune_call(stack, shape, shift, res, 6, s)[0]
+    else:
+        tn = _tune(tune)
     is_f32 = stack.dtype == torch.float32
-    if offsets is None and tn is None and not is_f32 and width == w0:
+    if od is None and tn is None and not is_f32 and width == w0:
         st = lib.dsk_deskew_u16(_vp(stack), _dims(shape), L.Geom(angle_deg, step_um, pixel_um),
                                 _vp(v), _vp(ps), _vp(pm), 0, s)
         L.check(st, "dsk_deskew_u16")
         return res
-    od = None if offsets is None else _offsets_dev(offsets, dev)
-    res["_offsets_dev"] = od          # keep alive until the kernel has read it
     if tn is not None or od is None:
         st = lib.dsk_deskew_offsets_tuned(_vp(stack), int(is_f32), _dims(shape), _vp(od),
                                           float(shift or 0.0), origin, _vp(v), _vp(ps), _vp(pm),

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdeskew.so")
-SOURCES = ["deskew.hip", "batch.hip", "rolling.hip", "view.hip", "affine.hip"]
+SOURCES = ["deskew.hip", "batch.hip", "tune.hip", "rolling.hip", "view.hip", "affine.hip"]
 ARCH = os.environ.get("DSK_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-ffp-contract=off",

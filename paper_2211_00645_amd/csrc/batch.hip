@@ -121,20 +121,6 @@ hipError_t launch_jobs(const JobDev *table, int n, int64_t total, int grid, cons
     return hipLaunchKernel((const void *)pick_kernel(t), dim3(grid), dim3(t.block), args, 0, s);
 }
 
-// ---- tuned-shape cache (JSON object, one entry per line) -----------------
-
-std::mutex g_cache_mu;
-
-std::string arch_name() {
-    int dev = 0;
-    hipDeviceProp_t p;
-    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
-        return "unknown";
-    std::string a(p.gcnArchName);
-    const size_t c = a.find(':');
-    return c == std::string::npos ? a : a.substr(0, c);
-}
-
 int log2_bucket(double v) { return v <= 1.0 ? 0 : (int)std::floor(std::log2(v)); }
 
 // Shape class: arch, job count, and log2 buckets of total output voxels
@@ -149,63 +135,6 @@ std::string shape_key(const dsk_job *jobs, int n) {
     std::snprintf(buf, sizeof buf, "%s/jobs%d/vox2^%d/planes2^%d", arch_name().c_str(), n,
                   log2_bucket(vox), log2_bucket(planes / n));
     return buf;
-}
-
-bool cache_lookup(const char *path, const std::string &key, dsk_tune *t, double *ms) {
-    std::FILE *f = std::fopen(path, "r");
-    if (!f) return false;
-    char line[512];
-    bool found = false;
-    while (std::fgets(line, sizeof line, f)) {
-        char k[256];
-        dsk_tune c{};
-        double m = 0.0;
-        if (std::sscanf(line,
-                        " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                        "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf}",
-                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu, &c.pace_gbs,
-                        &m) == 8 &&
-            key == k && tune_ok(c)) {
-            *t = c;
-            *ms = m;
-            found = true;
-        }
-    }
-    std::fclose(f);
-    return found;
-}
-
-void cache_store(const char *path, const std::string &key, const dsk_tune &t, double ms) {
-    // Keep every other entry, replace this key, rewrite the file.
-    std::vector<std::string> keep;
-    if (std::FILE *f = std::fopen(path, "r")) {
-        char line[512];
-        while (std::fgets(line, sizeof line, f)) {
-            char k[256];
-            if (std::sscanf(line, " \"%255[^\"]\":", k) == 1 && key != k) {
-                std::string s(line);
-                while (!s.empty() && (s.back() == '\n' || s.back() == ',')) s.pop_back();
-                keep.push_back(s);
-            }
-        }
-        std::fclose(f);
-    }
-    char ent[512];
-    std::snprintf(ent, sizeof ent,
-                  "  \"%s\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                  "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %.6f}",
-                  key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu,
-                  t.pace_gbs, ms);
-    keep.push_back(ent);
-    const std::string tmp = std::string(path) + ".tmp";
-    std::FILE *f = std::fopen(tmp.c_str(), "w");
-    if (!f) return;
-    std::fputs("{\n", f);
-    for (size_t i = 0; i < keep.size(); ++i)
-        std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
-    std::fputs("}\n", f);
-    std::fclose(f);
-    std::rename(tmp.c_str(), path);
 }
 
 // Launch shapes the autotuner times.
@@ -289,16 +218,10 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
         bt->tune = *tune;
         bt->best_ms = 0.0;
     } else {
-        const char *path = std::getenv("DSK_TUNE_CACHE");
         const std::string key = shape_key(jobs, n_jobs);
         dsk_tune t{};
         double ms = 0.0;
-        bool hit = false;
-        if (path && *path) {
-            std::lock_guard<std::mutex> lk(g_cache_mu);
-            hit = cache_lookup(path, key, &t, &ms);
-        }
-        if (!hit) {
+        if (!tune_cache_lookup(key, &t, &ms)) {
             double best = 1e300;
             for (const dsk_tune &c : candidates()) {
                 double m = 0.0;
@@ -310,10 +233,7 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
                 }
             }
             ms = best;
-            if (st == DSK_OK && path && *path) {
-                std::lock_guard<std::mutex> lk(g_cache_mu);
-                cache_store(path, key, t, ms);
-            }
+            if (st == DSK_OK) tune_cache_store(key, t, ms);
         }
         bt->tune = t;
         bt->best_ms = ms;

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <string>
 #include <type_traits>
 
 #include "deskew.h"
@@ -18,7 +19,9 @@ constexpr int64_t kMaxI32 = 2147483647;
 // holds up to about 5850 GB/s (5800: 0.851 ms); faster than that the
 // wavefronts fall behind the schedule, stop sleeping and drift apart
 // (0.83-0.95 ms, erratic), and boxes differ by a few percent, so the
-// default keeps a margin (5700: 0.862 ms, every launch within 1%).
+// default keeps a margin (5700: 0.862 ms, every launch within 1%).  Other
+// frames put the cliff elsewhere (5400-5800 GB/s); dsk_deskew_autotune
+// finds it for a given frame on the device at hand.
 constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
 
 inline bool dims_ok(dsk_dims d) {
@@ -32,17 +35,6 @@ inline bool tune_ok(const dsk_tune &t) {
     const bool u = t.unroll == 1 || t.unroll == 2 || t.unroll == 4;
     return b && j && u && (t.nt_store == 0 || t.nt_store == 1) && t.wg_per_cu >= 0 &&
            t.wg_per_cu <= 64 && t.pace_gbs >= 0 && t.pace_gbs <= 1000000;
-}
-
-// Plane pacing period in 1/256 ticks of the 100 MHz real-time clock: the
-// time the resident wavefronts take to move one plane's bytes at pace_gbs.
-// plane_bytes is one plane's traffic of the whole launch, resident the
-// fraction of its wavefronts that run at once.  0 = no pacing.
-inline uint32_t pace_tau256(double plane_bytes, double resident, int pace_gbs) {
-    if (pace_gbs <= 0 || !(plane_bytes > 0.0)) return 0;
-    const double r = resident > 1.0 ? 1.0 : (resident > 0.0 ? resident : 1.0);
-    const double t = plane_bytes * r / ((double)pace_gbs * 1e9) * 1e8 * 256.0;
-    return t >= 4.0e9 ? 4000000000u : (uint32_t)t;
 }
 
 // Compute units of the current device (cached per device).
@@ -132,6 +124,14 @@ struct InLayout {
 inline InLayout dense_layout(dsk_dims d) {
     return InLayout{d.cols, (int64_t)d.rows * d.cols, 0, (int64_t)d.planes * d.rows * d.cols};
 }
+
+// Tuned-shape cache (tune.hip): a JSON object in the file named by the
+// DSK_TUNE_CACHE environment variable, one "key": {shape, "ms"} entry per
+// line; without the variable nothing is read or written.  Keys begin with
+// the device architecture (arch_name).
+std::string arch_name();
+bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms);
+void tune_cache_store(const std::string &key, const dsk_tune &t, double ms);
 
 // Launchers (deskew.hip) used by the other translation units.
 int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs,

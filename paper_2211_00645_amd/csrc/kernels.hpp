@@ -346,7 +346,8 @@ struct VecTile {
     int gi[G], gfirst[G], glast[G];
     bool alive;
     uint64_t t0;                       // pacing origin (this wavefront's start)
-    uint32_t tau;                      // pacing period, 1/256 ticks (0 = none)
+    uint32_t tau;                      // pacing period per plane, 1/256 ticks (0 = none)
+    uint32_t taug;                     // the same per plane and group
     double acc[G][4];
     float mx[G][4];
     // chunk lane data (plane c0 + lane)
@@ -383,6 +384,8 @@ struct VecTile {
             const uint64_t t = ((uint64_t)a.tau_wg * (uint64_t)(left < cap ? left : cap)) >> 8;
             tau = t > 4000000000ull ? 4000000000u : (uint32_t)t;
         }
+        // a wavefront covers its G groups one after another, chunk by chunk
+        taug = tau / G;
         t0 = tau ? pace_clock() : 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -399,6 +402,13 @@ struct VecTile {
     }
 
     __device__ __forceinline__ int xcol(int g) const { return ca + 4 * gi[g]; }
+
+    // Pacing position (in plane-groups) of chunk plane li of group g in the
+    // chunk at c0: every earlier chunk is full, so G * c0 plane-groups lie
+    // before it, and the chunk's groups run one after another.
+    __device__ __forceinline__ int pace_pos(int g, int c0, int cn, int li) const {
+        return c0 * G + g * cn + li;
+    }
 
     // Positions [s0 + 4 gfirst, s0 + 4 glast + 5) of the wavefront's group g.
     __device__ __forceinline__ int cls_of(int s0, int g) const {
@@ -494,7 +504,7 @@ struct VecTile {
                 RawWin<TIn> nxt[U];
                 issue<U, MASK>(g, (k + 1) * U, cn, rpc, nxt);
                 // a paced wavefront sleeps with the next loads in flight
-                pace_until(t0, tau, c0 + k * U);
+                pace_until(t0, taug, pace_pos(g, c0, cn, k * U));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     float d[4];
@@ -583,7 +593,7 @@ struct VecTile {
                     if (op) {
                         float *o = op + xcol(g);
                         for (int li = 0; li < cn; ++li) {
-                            if ((li & 3) == 0) pace_until(t0, tau, c0 + li);
+                            if ((li & 3) == 0) pace_until(t0, taug, pace_pos(g, c0, cn, li));
                             store_f32x4<NT>(o, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
                             o += ostep;
                         }

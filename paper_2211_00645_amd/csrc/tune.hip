@@ -1,0 +1,222 @@
+// tune.hip -- launch-shape tuning: the on-disk cache of tuned shapes shared
+// by the batch and single-stack tuners, and the single-stack tuner.
+//
+// The vector kernel's plane pacing has a cliff: paced a little below the
+// rate the memory system sustains, every wavefront keeps to the schedule;
+// paced above it, the wavefronts fall behind, stop sleeping and drift apart,
+// and the launch runs at the unpaced speed, 10-25% slower.  Where the cliff
+// lies depends on the frame (how many waves a row needs, the read/write
+// mix) and differs by a few percent between devices, so a fixed pace either
+// leaves speed unused or sits past the cliff.  The tuner measures it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "common.hpp"
+#include "deskew.h"
+
+namespace dsk {
+
+namespace {
+std::mutex g_file_mu;
+}
+
+std::string arch_name() {
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess)
+        return "unknown";
+    std::string a(p.gcnArchName);
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms) {
+    const char *path = std::getenv("DSK_TUNE_CACHE");
+    if (!path || !*path) return false;
+    std::lock_guard<std::mutex> lk(g_file_mu);
+    std::FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    while (std::fgets(line, sizeof line, f)) {
+        char k[256];
+        dsk_tune c{};
+        double m = 0.0;
+        if (std::sscanf(line,
+                        " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
+                        "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf}",
+                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu,
+                        &c.pace_gbs, &m) == 8 &&
+            key == k && tune_ok(c)) {
+            *t = c;
+            *ms = m;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_store(const std::string &key, const dsk_tune &t, double ms) {
+    const char *path = std::getenv("DSK_TUNE_CACHE");
+    if (!path || !*path) return;
+    std::lock_guard<std::mutex> lk(g_file_mu);
+    // Keep every other entry, replace this key, rewrite the file.
+    std::vector<std::string> keep;
+    if (std::FILE *f = std::fopen(path, "r")) {
+        char line[512];
+        while (std::fgets(line, sizeof line, f)) {
+            char k[256];
+            if (std::sscanf(line, " \"%255[^\"]\":", k) == 1 && key != k) {
+                std::string s(line);
+                while (!s.empty() && (s.back() == '\n' || s.back() == ',')) s.pop_back();
+                keep.push_back(s);
+            }
+        }
+        std::fclose(f);
+    }
+    char ent[512];
+    std::snprintf(ent, sizeof ent,
+                  "  \"%s\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
+                  "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %.6f}",
+                  key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu,
+                  t.pace_gbs, ms);
+    keep.push_back(ent);
+    const std::string tmp = std::string(path) + ".tmp";
+    std::FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fputs("{\n", f);
+    for (size_t i = 0; i < keep.size(); ++i)
+        std::fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    std::fputs("}\n", f);
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+}  // namespace dsk
+
+using namespace dsk;
+
+namespace {
+
+// Shapes the single-stack tuner times.  With a volume: one and two 4-column
+// groups per lane, each unpaced and paced over the range where the cliff
+// lies on the frames measured (5000-6000 GB/s); the default shape is always
+// a candidate.  Without a volume nothing is paced: groups and pipeline
+// depth only.
+std::vector<dsk_tune> fwd_candidates(bool paced) {
+    std::vector<dsk_tune> c{kDefaultTune};
+    if (!paced) {
+        for (int pt : {4, 8})
+            for (int u : {2, 4}) c.push_back(dsk_tune{64, pt, 1, u, 0, 0});
+        return c;
+    }
+    for (int pt : {4, 8})
+        for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
+            c.push_back(dsk_tune{64, pt, 1, 2, 0, pace});
+    return c;
+}
+
+std::string fwd_key(int in_is_f32, dsk_dims d, int64_t width, bool offs, const float *vol,
+                    const float *psum, const float *pmax) {
+    char buf[200];
+    std::snprintf(buf, sizeof buf, "%s/fwd/%s/%dx%dx%d/w%lld/%s%s%s/%s", arch_name().c_str(),
+                  in_is_f32 ? "f32" : "u16", d.planes, d.rows, d.cols, (long long)width,
+                  vol ? "v" : "", psum ? "s" : "", pmax ? "m" : "", offs ? "offsets" : "uniform");
+    return buf;
+}
+
+std::mutex g_memo_mu;
+std::map<std::string, std::pair<dsk_tune, double>> g_memo;
+
+// Times every candidate `reps` times, round-robin (one launch of each per
+// round, so slow drifts of the device touch all alike), after one untimed
+// round.  Score: the upper-quartile time, so a shape that is fast only some
+// of the time (a pace at the cliff's edge) loses to one that is steady.
+int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in, int in_is_f32,
+                    dsk_dims d, const double *offs, double shift, int64_t origin, float *vol,
+                    float *psum, float *pmax, int64_t width, hipStream_t s,
+                    std::vector<double> *score) {
+    const size_t nc = cand.size();
+    std::vector<hipEvent_t> ev(nc + 1, nullptr);
+    int st = DSK_OK;
+    for (size_t i = 0; i <= nc && st == DSK_OK; ++i)
+        if (hipEventCreate(&ev[i]) != hipSuccess) st = DSK_EHIP;
+    std::vector<std::vector<float>> t(nc);
+    for (int round = 0; round <= reps && st == DSK_OK; ++round) {
+        if (hipEventRecord(ev[0], s) != hipSuccess) st = DSK_EHIP;
+        for (size_t i = 0; i < nc && st == DSK_OK; ++i) {
+            st = launch_forward(in, in_is_f32, d, offs, shift, origin, vol, psum, pmax, width,
+                                cand[i], s);
+            if (st == DSK_OK && hipEventRecord(ev[i + 1], s) != hipSuccess) st = DSK_EHIP;
+        }
+        if (st == DSK_OK && hipEventSynchronize(ev[nc]) != hipSuccess) st = DSK_EHIP;
+        for (size_t i = 0; i < nc && st == DSK_OK && round > 0; ++i) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = DSK_EHIP;
+            t[i].push_back(ms);
+        }
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != DSK_OK) return st;
+    score->assign(nc, 0.0);
+    for (size_t i = 0; i < nc; ++i) {
+        std::sort(t[i].begin(), t[i].end());
+        (*score)[i] = t[i][(size_t)(3 * reps) / 4];
+    }
+    return DSK_OK;
+}
+
+}  // namespace
+
+extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
+                                   const double *offsets_dev, double shift_px, int64_t origin,
+                                   float *vol, float *psum, float *pmax, int64_t out_width,
+                                   int reps, hipStream_t stream, dsk_tune *tune, double *ms) {
+    if (!tune || out_width <= 0 || reps < 3 || reps > 64) return DSK_EINVAL;
+    if (!in || !dims_ok(d) || (!vol && !psum && !pmax)) return DSK_EINVAL;
+    if (!offsets_dev && !std::isfinite(shift_px)) return DSK_EINVAL;
+    const std::string key =
+        fwd_key(in_is_f32, d, out_width, offsets_dev != nullptr, vol, psum, pmax);
+    {
+        std::lock_guard<std::mutex> lk(g_memo_mu);
+        auto it = g_memo.find(key);
+        if (it != g_memo.end()) {
+            *tune = it->second.first;
+            if (ms) *ms = it->second.second;
+            return DSK_OK;
+        }
+    }
+    dsk_tune best{};
+    double best_ms = 0.0;
+    if (!tune_cache_lookup(key, &best, &best_ms)) {
+        const std::vector<dsk_tune> cand = fwd_candidates(vol != nullptr);
+        std::vector<double> score;
+        const int st = time_candidates(cand, reps, in, in_is_f32 ? 1 : 0, d, offsets_dev,
+                                       shift_px, origin, vol, psum, pmax, out_width, stream,
+                                       &score);
+        if (st != DSK_OK) return st;
+        size_t bi = 0;
+        for (size_t i = 1; i < cand.size(); ++i)
+            if (score[i] < score[bi]) bi = i;
+        best = cand[bi];
+        best_ms = score[bi];
+        tune_cache_store(key, best, best_ms);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_memo_mu);
+        g_memo[key] = {best, best_ms};
+    }
+    *tune = best;
+    if (ms) *ms = best_ms;
+    return DSK_OK;
+}

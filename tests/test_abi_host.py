@@ -109,6 +109,28 @@ def test_launch_entry_points_reject_bad_arguments_before_any_launch():
     assert lib.dsk_batch_destroy(None) == L.DSK_EINVAL
 
 
+def test_autotune_rejects_bad_arguments_before_any_device_call():
+    lib = L.lib()
+    d = L.Dims(4, 2, 8)
+    fake = ctypes.c_void_p(0x1000)
+    t = L.Tune()
+    ms = ctypes.c_double()
+
+    def call(in_=fake, dims=d, offs=None, shift=0.5, vol=fake, width=12, reps=6, tune=True):
+        return lib.dsk_deskew_autotune(in_, 0, dims, offs, shift, 0, vol, None, None, width,
+                                       reps, None, ctypes.byref(t) if tune else None,
+                                       ctypes.byref(ms))
+
+    assert call(tune=False) == L.DSK_EINVAL
+    assert call(reps=2) == L.DSK_EINVAL
+    assert call(reps=65) == L.DSK_EINVAL
+    assert call(width=0) == L.DSK_EINVAL
+    assert call(in_=None) == L.DSK_EINVAL
+    assert call(vol=None) == L.DSK_EINVAL
+    assert call(dims=L.Dims(4, 0, 8)) == L.DSK_EINVAL
+    assert call(shift=float("nan")) == L.DSK_EINVAL
+
+
 def test_rolling_tree_size():
     lib = L.lib()
     f = lambda n: lib.dsk_rolling_tree_bytes(L.Dims(n, 3, 5), 7) // (3 * 7 * 4)

@@ -1,0 +1,78 @@
+"""The single-stack launch-shape tuner: it picks one of its candidate
+shapes, the forward with that shape gives bitwise the default shape's
+result (and the oracle's, within the forward's bar), the choice is
+remembered per frame, and the on-disk cache round-trips it."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2211_00645_amd as dsk
+from paper_2211_00645_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+PACES = {0, 5000, 5200, 5400, 5600, 5700, 5800, 6000}
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _valid(t):
+    return (t["block"] == 64 and t["per_thread"] in (4, 8) and t["nt_store"] == 1
+            and t["unroll"] in (2, 4) and t["wg_per_cu"] == 0 and t["pace_gbs"] in PACES)
+
+
+@pytest.mark.parametrize("shape,angle,step", [((96, 40, 300), 35.0, 0.4),
+                                              ((64, 33, 257), 30.0, 0.1)])
+def test_tuned_shape_gives_the_default_result(shape, angle, step):
+    _say(f"autotune {shape} {angle} {step}")
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 11, device=DEV)
+    got = dsk.autotune(st, angle, step, 0.115, reps=3)
+    assert _valid(got["tune"]) and got["ms"] > 0.0
+    ref = dsk.deskew(st, angle, step, 0.115)
+    res = dsk.deskew(st, angle, step, 0.115, tune=got["tune"])
+    auto = dsk.deskew(st, angle, step, 0.115, tune="auto")
+    torch.cuda.synchronize()
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(res[k], ref[k]), k
+        assert torch.equal(auto[k], ref[k]), k
+    # and the tuned result against the oracle, on the projections
+    s = dsk.shift_px(angle, step, 0.115)
+    o = oracle.deskew(st.cpu().numpy(), s * np.arange(shape[0]), origin=res["origin"],
+                      width=res["width"])
+    np.testing.assert_allclose(res["psum"].cpu().numpy(), o["psum"], rtol=1e-5, atol=1e-3)
+    np.testing.assert_allclose(res["pmax"].cpu().numpy(), o["pmax"], rtol=1e-5, atol=1e-3)
+
+
+def test_choice_is_remembered_without_launching():
+    shape = (80, 24, 256)
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 5, device=DEV)
+    first = dsk.autotune(st, 35.0, 0.4, 0.115, reps=3)
+    # a second call with other buffers of the same frame launches nothing,
+    # so the fresh volume keeps its fill
+    width = dsk.plan(shape, shift=dsk.shift_px(35.0, 0.4, 0.115))[0]
+    out = {"vol": torch.full((shape[0], shape[1], width), -7.0, device=DEV)}
+    again = dsk.autotune(st, 35.0, 0.4, 0.115, out=out, reps=3)
+    torch.cuda.synchronize()
+    assert again == first
+    assert bool((out["vol"] == -7.0).all())
+
+
+def test_disk_cache_round_trip(tmp_path, monkeypatch):
+    path = tmp_path / "tune.json"
+    monkeypatch.setenv("DSK_TUNE_CACHE", str(path))
+    shape = (72, 20, 264)            # a frame no other test tunes
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 8, device=DEV)
+    got = dsk.autotune(st, 35.0, 0.4, 0.115, psum=False, reps=3)
+    data = json.loads(path.read_text())
+    keys = [k for k in data if "/fwd/u16/72x20x264/" in k]
+    assert len(keys) == 1 and keys[0].endswith("/vm/uniform")
+    ent = data[keys[0]]
+    assert {k: ent[k] for k in got["tune"]} == got["tune"]
+    assert abs(ent["ms"] - got["ms"]) < 1e-6
