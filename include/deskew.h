@@ -202,10 +202,19 @@ int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims d,
 
 /* ---------------------------------------------------------------------
  * Ragged batches: many uint16 stacks of different sizes and geometries in
- * one persistent launch (one workgroup per compute-unit slot walks a shared
- * list of (stack, row, column-tile) items).  Each job's outputs are bitwise
- * identical to its own dsk_deskew_offsets_u16 / dsk_deskew_u16 call.
+ * one graph launch.  The graph holds either one persistent kernel (one
+ * workgroup per compute-unit slot walks a shared list of (stack, row,
+ * column-tile) items: no per-launch tails, best for many small stacks) or
+ * one plain paced launch per job (each job's wavefronts keep to one
+ * schedule: best for large stacks), whichever the autotuner measures
+ * faster.  Each job's outputs are bitwise identical to its own
+ * dsk_deskew_offsets_u16 / dsk_deskew_u16 call in either mode.
  * ------------------------------------------------------------------- */
+enum {
+    DSK_BATCH_PERSISTENT = 0,  /* one persistent kernel over all jobs */
+    DSK_BATCH_PER_JOB = 1      /* one plain launch per job */
+};
+
 typedef struct {
     const uint16_t *in;         /* device stack [planes][rows][cols] */
     dsk_dims dims;
@@ -219,22 +228,29 @@ typedef struct {
 typedef struct dsk_batch dsk_batch;
 
 /* Build a batch: validates the jobs, uploads the job table (device memory
- * owned by the batch), picks the launch shape (tune != NULL: use it; NULL:
- * time the candidate shapes on `stream`, which runs the jobs -- outputs are
- * then already written), and captures the launch in a HIP graph.  Host
- * call; allocates and synchronises `stream`. */
+ * owned by the batch), picks the execution (tune != NULL: the persistent
+ * kernel in that shape; NULL: time the persistent kernel's candidate shapes
+ * and the per-job mode on `stream` -- which runs the jobs, so outputs are
+ * then already written -- and keep the fastest, remembered per batch shape
+ * class in the DSK_TUNE_CACHE file when that variable is set), and captures
+ * the launch in a HIP graph.  Host call; allocates and synchronises
+ * `stream`. */
 int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune *tune,
                      hipStream_t stream, dsk_batch **out);
 
 /* Replay the captured graph on `stream` (asynchronous). */
 int dsk_batch_launch(dsk_batch *batch, hipStream_t stream);
 
-/* Launch the persistent kernel directly, without the graph. */
+/* The same launches directly, without the graph. */
 int dsk_batch_launch_direct(dsk_batch *batch, hipStream_t stream);
 
-/* The launch shape the batch uses, and the autotuner's best time (ms, 0
- * when the shape was given). */
+/* The persistent kernel's launch shape, and the autotuner's best time (ms,
+ * 0 when the shape was given). */
 int dsk_batch_get_tune(const dsk_batch *batch, dsk_tune *tune, double *ms);
+
+/* The execution mode the batch uses (DSK_BATCH_PERSISTENT or
+ * DSK_BATCH_PER_JOB) into *mode (host). */
+int dsk_batch_get_mode(const dsk_batch *batch, int *mode);
 
 int dsk_batch_destroy(dsk_batch *batch);
 

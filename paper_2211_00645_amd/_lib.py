@@ -73,6 +73,7 @@ _SIGS = {
     "dsk_batch_launch": (ctypes.c_int, [c_vp, c_vp]),
     "dsk_batch_launch_direct": (ctypes.c_int, [c_vp, c_vp]),
     "dsk_batch_get_tune": (ctypes.c_int, [c_vp, ctypes.POINTER(Tune), ctypes.POINTER(c_dbl)]),
+    "dsk_batch_get_mode": (ctypes.c_int, [c_vp, ctypes.POINTER(ctypes.c_int)]),
     "dsk_batch_destroy": (ctypes.c_int, [c_vp]),
     "dsk_jobs_table_bytes": (c_sz, [ctypes.c_int]),
     "dsk_rolling_tree_bytes": (c_sz, [Dims, c_i64]),

@@ -1,11 +1,13 @@
 """Ragged batches: many uint16 stacks of different shapes and geometries
-deskewed in ONE persistent kernel launch, captured once in a HIP graph.
+deskewed by ONE graph launch.
 
-The launch shape (threads per workgroup, columns per thread, plane unroll,
-streaming stores) is picked by the library's autotuner, which times the
-candidate shapes on the batch itself and caches the winner per device
-architecture and batch shape class in a JSON file (``DSK_TUNE_CACHE``).
-Each job's outputs are bitwise identical to its own single-stack call.
+The graph holds either one persistent kernel over all jobs or one plain
+paced launch per job.  The library's autotuner times the persistent
+kernel's candidate shapes (threads per workgroup, columns per thread, plane
+unroll, pacing) and the per-job mode on the batch's own buffers, keeps the
+fastest, and caches the choice per device architecture and batch shape
+class in a JSON file (``DSK_TUNE_CACHE``).  Each job's outputs are bitwise
+identical to its own single-stack call in either mode.
 """
 from __future__ import annotations
 
@@ -90,6 +92,15 @@ class Batch:
         L.check(L.lib().dsk_batch_get_tune(self._h, ctypes.byref(t), ctypes.byref(ms)),
                 "dsk_batch_get_tune")
         return dict(t.as_dict(), tuned_ms=ms.value)
+
+    @property
+    def mode(self):
+        """"persistent" (one kernel over all jobs) or "per_job" (one plain
+        launch per job), as the autotuner chose (persistent when a shape
+        was given)."""
+        m = ctypes.c_int()
+        L.check(L.lib().dsk_batch_get_mode(self._h, ctypes.byref(m)), "dsk_batch_get_mode")
+        return "per_job" if m.value == 1 else "persistent"
 
     def launch(self, stream=None, graph=True):
         """Enqueue the whole batch (graph replay, or a direct launch)."""

@@ -1,6 +1,7 @@
-// batch.hip -- ragged batches of uint16 stacks in one persistent launch:
-// device job table, launch-shape autotuner with an on-disk cache, and HIP
-// graph capture of the launch.
+// batch.hip -- ragged batches of uint16 stacks in one graph launch: either
+// one persistent kernel over all jobs (device job table) or one plain paced
+// launch per job, whichever the autotuner measures faster on the batch's own
+// buffers (on-disk cache of the choice), captured in a HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -12,6 +13,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "tune.hpp"
 #include "deskew.h"
 #include "kernels.hpp"
 
@@ -21,6 +23,7 @@ struct dsk_batch {
     int device = 0;
     int n_jobs = 0;
     std::vector<dsk_job> jobs;
+    int mode = DSK_BATCH_PERSISTENT;
     dsk_tune tune{};
     double best_ms = 0.0;
     int64_t total_tiles = 0;
@@ -190,6 +193,49 @@ int time_shape(dsk_batch *bt, const dsk_tune &t, hipStream_t s, int reps, double
     return DSK_OK;
 }
 
+// Per-job mode: every job as its own plain launch in the library default
+// shape (paced, so each job's wavefronts keep to one schedule).
+int launch_per_job(const dsk_batch *bt, hipStream_t s) {
+    for (const dsk_job &j : bt->jobs) {
+        const int st = launch_forward(j.in, 0, j.dims, j.offsets_dev, j.shift_px, j.origin, j.vol,
+                                      j.psum, j.pmax, j.out_width, kDefaultTune, s);
+        if (st != DSK_OK) return st;
+    }
+    return DSK_OK;
+}
+
+int launch_mode(dsk_batch *bt, hipStream_t s) {
+    if (bt->mode == DSK_BATCH_PER_JOB) return launch_per_job(bt, s);
+    return hip_status(
+        launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, bt->tune, s));
+}
+
+// Best of `reps` timed runs (ms) of the per-job mode, after one untimed run.
+int time_per_job(dsk_batch *bt, hipStream_t s, int reps, double *ms) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess) return DSK_EHIP;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return DSK_EHIP;
+    }
+    double best = 1e300;
+    int st = launch_per_job(bt, s);
+    for (int i = 0; i < reps && st == DSK_OK; ++i) {
+        if (hipEventRecord(a, s) != hipSuccess) st = DSK_EHIP;
+        if (st == DSK_OK) st = launch_per_job(bt, s);
+        if (st == DSK_OK && hipEventRecord(b, s) != hipSuccess) st = DSK_EHIP;
+        if (st == DSK_OK && hipEventSynchronize(b) != hipSuccess) st = DSK_EHIP;
+        float f = 0.0f;
+        if (st == DSK_OK && hipEventElapsedTime(&f, a, b) != hipSuccess) st = DSK_EHIP;
+        if (st == DSK_OK && f < best) best = f;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != DSK_OK) return st;
+    *ms = best;
+    return DSK_OK;
+}
+
 }  // namespace
 
 extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune *tune,
@@ -221,7 +267,8 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
         const std::string key = shape_key(jobs, n_jobs);
         dsk_tune t{};
         double ms = 0.0;
-        if (!tune_cache_lookup(key, &t, &ms)) {
+        int mode = DSK_BATCH_PERSISTENT;
+        if (!tune_cache_lookup(key, &t, &ms, &mode)) {
             double best = 1e300;
             for (const dsk_tune &c : candidates()) {
                 double m = 0.0;
@@ -232,11 +279,18 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
                     t = c;
                 }
             }
+            double m = 0.0;
+            if (st == DSK_OK) st = time_per_job(bt, stream, 2, &m);
+            if (st == DSK_OK && m < best) {
+                best = m;
+                mode = DSK_BATCH_PER_JOB;
+            }
             ms = best;
-            if (st == DSK_OK) tune_cache_store(key, t, ms);
+            if (st == DSK_OK) tune_cache_store(key, t, ms, mode);
         }
         bt->tune = t;
         bt->best_ms = ms;
+        bt->mode = mode;
     }
     if (st == DSK_OK) st = upload_table(bt, bt->tune, stream);
     if (st == DSK_OK) {
@@ -245,10 +299,9 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
         hipError_t e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid,
-                                        bt->tune, cap);
+            const int lst = launch_mode(bt, cap);
             e = hipStreamEndCapture(cap, &bt->graph);
-            if (le != hipSuccess) e = le;
+            if (lst != DSK_OK) e = hipErrorLaunchFailure;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0);
         if (cap) (void)hipStreamDestroy(cap);
@@ -269,8 +322,13 @@ extern "C" int dsk_batch_launch(dsk_batch *bt, hipStream_t stream) {
 
 extern "C" int dsk_batch_launch_direct(dsk_batch *bt, hipStream_t stream) {
     if (!bt || !bt->table_dev) return DSK_EINVAL;
-    return hip_status(
-        launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, bt->tune, stream));
+    return launch_mode(bt, stream);
+}
+
+extern "C" int dsk_batch_get_mode(const dsk_batch *bt, int *mode) {
+    if (!bt || !mode) return DSK_EINVAL;
+    *mode = bt->mode;
+    return DSK_OK;
 }
 
 extern "C" int dsk_batch_get_tune(const dsk_batch *bt, dsk_tune *tune, double *ms) {

@@ -4,7 +4,6 @@
 
 #include <cmath>
 #include <cstdint>
-#include <string>
 #include <type_traits>
 
 #include "deskew.h"
@@ -124,14 +123,6 @@ struct InLayout {
 inline InLayout dense_layout(dsk_dims d) {
     return InLayout{d.cols, (int64_t)d.rows * d.cols, 0, (int64_t)d.planes * d.rows * d.cols};
 }
-
-// Tuned-shape cache (tune.hip): a JSON object in the file named by the
-// DSK_TUNE_CACHE environment variable, one "key": {shape, "ms"} entry per
-// line; without the variable nothing is read or written.  Keys begin with
-// the device architecture (arch_name).
-std::string arch_name();
-bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms);
-void tune_cache_store(const std::string &key, const dsk_tune &t, double ms);
 
 // Launchers (deskew.hip) used by the other translation units.
 int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs,

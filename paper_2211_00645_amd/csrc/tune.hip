@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "tune.hpp"
 #include "deskew.h"
 
 namespace dsk {
@@ -38,7 +39,7 @@ std::string arch_name() {
     return c == std::string::npos ? a : a.substr(0, c);
 }
 
-bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms) {
+bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms, int *mode) {
     const char *path = std::getenv("DSK_TUNE_CACHE");
     if (!path || !*path) return false;
     std::lock_guard<std::mutex> lk(g_file_mu);
@@ -50,14 +51,17 @@ bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms) {
         char k[256];
         dsk_tune c{};
         double m = 0.0;
-        if (std::sscanf(line,
-                        " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                        "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf}",
-                        k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu,
-                        &c.pace_gbs, &m) == 8 &&
-            key == k && tune_ok(c)) {
+        int md = 0;
+        const int got = std::sscanf(
+            line,
+            " \"%255[^\"]\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
+            "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf, \"mode\": %d}",
+            k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu, &c.pace_gbs, &m,
+            &md);
+        if (got >= 8 && key == k && tune_ok(c) && md >= 0 && md <= 1) {
             *t = c;
             *ms = m;
+            if (mode) *mode = got == 9 ? md : 0;
             found = true;
         }
     }
@@ -65,7 +69,7 @@ bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms) {
     return found;
 }
 
-void tune_cache_store(const std::string &key, const dsk_tune &t, double ms) {
+void tune_cache_store(const std::string &key, const dsk_tune &t, double ms, int mode) {
     const char *path = std::getenv("DSK_TUNE_CACHE");
     if (!path || !*path) return;
     std::lock_guard<std::mutex> lk(g_file_mu);
@@ -86,9 +90,10 @@ void tune_cache_store(const std::string &key, const dsk_tune &t, double ms) {
     char ent[512];
     std::snprintf(ent, sizeof ent,
                   "  \"%s\": {\"block\": %d, \"per_thread\": %d, \"nt_store\": %d, "
-                  "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %.6f}",
+                  "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %.6f, "
+                  "\"mode\": %d}",
                   key.c_str(), t.block, t.per_thread, t.nt_store, t.unroll, t.wg_per_cu,
-                  t.pace_gbs, ms);
+                  t.pace_gbs, ms, mode);
     keep.push_back(ent);
     const std::string tmp = std::string(path) + ".tmp";
     std::FILE *f = std::fopen(tmp.c_str(), "w");
@@ -198,7 +203,7 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
     }
     dsk_tune best{};
     double best_ms = 0.0;
-    if (!tune_cache_lookup(key, &best, &best_ms)) {
+    if (!tune_cache_lookup(key, &best, &best_ms, nullptr)) {
         const std::vector<dsk_tune> cand = fwd_candidates(vol != nullptr);
         std::vector<double> score;
         const int st = time_candidates(cand, reps, in, in_is_f32 ? 1 : 0, d, offsets_dev,
@@ -210,7 +215,7 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
             if (score[i] < score[bi]) bi = i;
         best = cand[bi];
         best_ms = score[bi];
-        tune_cache_store(key, best, best_ms);
+        tune_cache_store(key, best, best_ms, 0);
     }
     {
         std::lock_guard<std::mutex> lk(g_memo_mu);

@@ -69,12 +69,35 @@ def test_graph_replays_match_single_launches(small, tmp_path):
     # a second batch of the same shape class hits the cache (no timing)
     b2 = Batch(stacks, geoms, cache_path=cache)
     assert b2.tune["block"] == t["block"] and b2.tune["per_thread"] == t["per_thread"]
+    mode = b.mode
+    assert b2.mode == mode
     b2.launch(graph=False)
     torch.cuda.synchronize()
     for o, s in zip(b2.outputs, solo):
         assert torch.equal(o["vol"], s["vol"])
     b.close()
     b2.close()
+    # the remembered choice decides the mode: flip it, and the other mode's
+    # graph gives the same bits replay after replay
+    (key, ent), = json.loads(cache.read_text()).items()
+    other = "per_job" if mode == "persistent" else "persistent"
+    ent["mode"] = 1 if other == "per_job" else 0
+    cache.write_text("{\n" + f'  "{key}": ' + json.dumps(ent) + "\n}\n")
+    b3 = Batch(stacks, geoms, cache_path=cache)
+    _say(f"batch: forced mode {other}")
+    assert b3.mode == other
+    for rep in range(2):
+        for o in b3.outputs:
+            for k in ("vol", "psum", "pmax"):
+                o[k].fill_(-1.0)
+        b3.launch()
+        junk = torch.randn(1 << 20, device=DEV).sum()
+        torch.cuda.synchronize()
+        for i, (o, s) in enumerate(zip(b3.outputs, solo)):
+            for k in ("vol", "psum", "pmax"):
+                assert torch.equal(o[k], s[k]), (other, rep, i, k)
+        del junk
+    b3.close()
 
 
 @pytest.mark.parametrize("tune", [dict(block=64, per_thread=4, unroll=1, nt_store=0),
