@@ -261,7 +261,10 @@ size_t dsk_jobs_table_bytes(int n_jobs);
  * table_host: host buffer of dsk_jobs_table_bytes(n_jobs) bytes, ideally
  * pinned; it is encoded here and copied to table_dev with hipMemcpyAsync on
  * `stream`, so it must stay unchanged until that copy completes (record an
- * event).  table_dev: device buffer of the same size.  tune may be NULL. */
+ * event).  table_dev: device buffer of the same size.  tune NULL: the
+ * library default, paced only when every job has one frame (dims and
+ * out_width), since pacing helps wavefronts that move in lockstep and
+ * holds back a grid whose tiles belong to stacks of different sizes. */
 int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host,
                     void *table_dev, size_t table_bytes, const dsk_tune *tune,
                     hipStream_t stream);

@@ -356,11 +356,22 @@ extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host
                                hipStream_t stream) {
     if (!jobs || n_jobs <= 0 || !table_host || !table_dev) return DSK_EINVAL;
     if (table_bytes < dsk_jobs_table_bytes(n_jobs)) return DSK_ESHAPE;
-    const dsk_tune t = tune ? *tune : kDefaultTune;
+    dsk_tune t = tune ? *tune : kDefaultTune;
     if (!tune_ok(t)) return DSK_EINVAL;
     for (int i = 0; i < n_jobs; ++i) {
         const int st = validate_job(jobs[i]);
         if (st != DSK_OK) return st;
+    }
+    if (!tune) {
+        // wavefronts of different stacks cannot keep one schedule
+        for (int i = 1; i < n_jobs; ++i) {
+            const dsk_job &a = jobs[0], &b = jobs[i];
+            if (a.dims.planes != b.dims.planes || a.dims.rows != b.dims.rows ||
+                a.dims.cols != b.dims.cols || a.out_width != b.out_width) {
+                t.pace_gbs = 0;
+                break;
+            }
+        }
     }
     JobDev *host = (JobDev *)table_host;
     const int64_t total = encode_table(jobs, n_jobs, t, host);

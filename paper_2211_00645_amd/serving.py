@@ -367,7 +367,9 @@ class GPUExecutor:
             proj = sum(2 * rows * w for (_, _, _, rows, w) in items)
             st = self.staging[slot]
             if st is None or st.numel() < proj:
-                st = torch.empty((max(proj, 1 << 20),), dtype=torch.float32, pin_memory=True)
+                # pinned allocation is slow: grow at least twofold
+                grow = max(proj, 1 << 20, 2 * (st.numel() if st is not None else 0))
+                st = torch.empty((grow,), dtype=torch.float32, pin_memory=True)
                 self.staging[slot] = st
             jobs, outs, host = [], [], []
             off = 0
