@@ -114,9 +114,10 @@ namespace {
 
 // Shapes the single-stack tuner times.  With a volume: one and two 4-column
 // groups per lane, each unpaced and paced over the range where the cliff
-// lies on the frames measured (5000-6000 GB/s); the default shape is always
-// a candidate.  Without a volume nothing is paced: groups and pipeline
-// depth only.
+// lies on the frames measured (5000-6000 GB/s; one group per lane in 100
+// GB/s steps from 5400, where most frames put it); the default shape is
+// always a candidate.  Without a volume nothing is paced: groups and
+// pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
     std::vector<dsk_tune> c{kDefaultTune};
     if (!paced) {
@@ -124,9 +125,10 @@ std::vector<dsk_tune> fwd_candidates(bool paced) {
             for (int u : {2, 4}) c.push_back(dsk_tune{64, pt, 1, u, 0, 0});
         return c;
     }
-    for (int pt : {4, 8})
-        for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
-            c.push_back(dsk_tune{64, pt, 1, 2, 0, pace});
+    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5800, 5900, 6000})
+        c.push_back(dsk_tune{64, 4, 1, 2, 0, pace});
+    for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
+        c.push_back(dsk_tune{64, 8, 1, 2, 0, pace});
     return c;
 }
 
