@@ -188,16 +188,31 @@ def bench_batch(torch, dsk, synth):
                       "same output buffers; medians"}
 
 
+def _b2b_ms(torch, fn, reps):
+    """Average time per call of `reps` calls back to back (after 3 warm-up
+    calls): kernel time without the host's launch latency."""
+    for _ in range(3):
+        fn()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
 def bench_autograd(torch, dsk, synth):
-    """Forward (float32) + fused backward on 256 x 512 x 1024, frame 1793."""
+    """Forward (float32, tuned shape) + fused backward on 256 x 512 x 1024,
+    frame 1793; calls back to back."""
     n, r, c, w = 256, 512, 1024, 1793
     st = synth.blob_stack((n, r, c), 2000, 4, device="cuda", dtype="f32")
     offs = torch.arange(n, dtype=torch.float64, device="cuda") * dsk.shift_px(30.0, STEP, PIXEL)
     out = {"vol": torch.empty((n, r, w), device="cuda")}
     gd = torch.empty((n, r, w), device="cuda").uniform_()
-    fwd = _median_ms(torch, lambda: dsk.deskew(st, offsets=offs, origin=0, width=w, out=out,
-                                                psum=False, pmax=False), 10)
-    bwd = _median_ms(torch, lambda: dsk.backward(st, gd, offs, 0), 10)
+    fwd = _b2b_ms(torch, lambda: dsk.deskew(st, offsets=offs, origin=0, width=w, out=out,
+                                             psum=False, pmax=False, tune="auto"), 20)
+    bwd = _b2b_ms(torch, lambda: dsk.backward(st, gd, offs, 0), 20)
     del st, out, gd
     torch.cuda.empty_cache()
     fb = 4 * n * r * c + 4 * n * r * w

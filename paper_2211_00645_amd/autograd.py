@@ -18,12 +18,14 @@ from . import api
 
 
 class DeskewFunction(torch.autograd.Function):
-    """vol = D(stack; offsets) on a fixed frame (origin, width)."""
+    """vol = D(stack; offsets) on a fixed frame (origin, width).  ``tune``:
+    the forward's launch shape (None: library default; "auto": the shape
+    the library's tuner picks for this frame, measured once)."""
 
     @staticmethod
-    def forward(ctx, stack, offsets, origin, width):
+    def forward(ctx, stack, offsets, origin, width, tune=None):
         out = api.deskew(stack, offsets=offsets.detach(), origin=int(origin), width=int(width),
-                         psum=False, pmax=False)
+                         psum=False, pmax=False, tune=tune)
         ctx.save_for_backward(stack, offsets)
         ctx.origin = int(origin)
         return out["vol"]
@@ -33,16 +35,17 @@ class DeskewFunction(torch.autograd.Function):
         stack, offsets = ctx.saved_tensors
         need_in, need_off = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_in or need_off):
-            return None, None, None, None
+            return None, None, None, None, None
         gi, go = api.backward(stack, grad_vol.contiguous(), offsets.detach().contiguous(),
                               ctx.origin, grad_in=need_in, grad_offsets=need_off)
-        return gi, go, None, None
+        return gi, go, None, None, None
 
 
 def deskew_volume(stack: torch.Tensor, offsets: torch.Tensor, origin: int,
-                  width: int) -> torch.Tensor:
-    """Differentiable deskewed volume of a float32 CUDA stack."""
-    return DeskewFunction.apply(stack, offsets, origin, width)
+                  width: int, tune=None) -> torch.Tensor:
+    """Differentiable deskewed volume of a float32 CUDA stack (``tune`` as
+    :class:`DeskewFunction`)."""
+    return DeskewFunction.apply(stack, offsets, origin, width, tune)
 
 
 def offsets_from_angle(angle_deg: torch.Tensor, n_planes: int, step_um: float,

@@ -179,6 +179,20 @@ def test_autograd_chain_rule_to_angle(cfg4):
     assert torch.equal(st2.grad, dsk.adjoint(tgt[:8].contiguous(), offs.detach()[:8], 0, C4))
 
 
+def test_tuned_forward_same_bits_and_gradient(cfg4):
+    st, _ = cfg4
+    angle = torch.tensor(30.7, dtype=torch.float64, device=DEV, requires_grad=True)
+    offs = ag.offsets_from_angle(angle, N4, STEP, PIXEL)
+    ref = ag.deskew_volume(st, offs, 0, W4)
+    vol = ag.deskew_volume(st, offs, 0, W4, tune="auto")
+    assert torch.equal(vol, ref)
+    vol.sum().backward()
+    g_auto = float(angle.grad)
+    angle.grad = None
+    ag.deskew_volume(st, ag.offsets_from_angle(angle, N4, STEP, PIXEL), 0, W4).sum().backward()
+    assert float(angle.grad) == g_auto
+
+
 def test_calibration_recovers_32_degrees(cfg4):
     st, sn = cfg4
     _say("calibration: oracle ground truth at 32 deg")
