@@ -56,7 +56,8 @@ def plan_job(stack, angle_deg, step_um, pixel_um, vol=True, psum=True, pmax=True
 
 
 class Batch:
-    """One persistent launch over ragged stacks.
+    """One graph launch over ragged stacks (persistent kernel or one launch
+    per job, see :attr:`mode`).
 
     ``stacks``: list of contiguous uint16 CUDA tensors [planes][rows][cols];
     ``geoms``: list of (angle_deg, step_um, pixel_um).  ``tune``: launch
