@@ -94,9 +94,58 @@ def cpu_baseline(stack_host, target_s):
     vox = N * rows * w * reps
     what = (f"rows 0..{rows} of" if rows < R else f"{reps} passes over") + \
         f" the {N}x{R}x{C} stack (all {N} planes, W={w})"
-    return {"value": vox / dt, "unit": "voxels/s", "cores": oracle.threads(), "kind": "oracle",
-            "sample": f"{what}, FP64 volume + sum + max projections, {dt:.2f} s",
-            "seconds": dt}
+    res = {"value": vox / dt, "unit": "voxels/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"{what}, FP64 volume + sum + max projections, {dt:.2f} s",
+           "seconds": dt}
+    # the same on one core, over fewer rows (about a tenth of the time)
+    nt = oracle.threads()
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.deskew(stack_host, offs, rows=(0, 1))
+        one_row = time.perf_counter() - t0
+        rows1 = int(max(1, min(R, round(0.1 * target_s / max(one_row, 1e-6)))))
+        t0 = time.perf_counter()
+        oracle.deskew(stack_host, offs, rows=(0, rows1))
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(nt)
+    res["value_1core"] = N * rows1 * w / dt1
+    res["sample_1core"] = f"rows 0..{rows1} on 1 thread, {dt1:.2f} s"
+    res["host_cpus"] = os.cpu_count()
+    res["cpu_model"] = _cpu_model()
+    return res
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def config1_times(torch, dsk, synth):
+    """The small stack (64 x 128 x 256 uint16, 30 deg, 0.4 um, 0.115 um; 50
+    spots, seed 0): GPU forward (calls back to back) and the FP64 oracle on
+    the host cores, median of 3.  Correctness-sized: it fits in the on-die
+    cache, so it says nothing about HBM."""
+    import oracle
+    shp = (64, 128, 256)
+    st = synth.blob_stack(shp, 50, 0, device="cuda")
+    gpu = _b2b_ms(torch, lambda: dsk.deskew(st, 30.0, 0.4, 0.115), 50)
+    host = st.cpu().numpy()
+    offs = oracle.offsets_uniform(shp[0], oracle.shift_px(30.0, 0.4, 0.115))
+    ts = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        oracle.deskew(host, offs)
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"workload": "64x128x256 uint16, 30 deg, W=446", "gpu_ms": gpu,
+            "oracle_ms": statistics.median(ts), "oracle_threads": oracle.threads()}
 
 
 def copy_ceiling(torch, nbytes=4 << 30, reps=5):
@@ -213,13 +262,27 @@ def bench_autograd(torch, dsk, synth):
     fwd = _b2b_ms(torch, lambda: dsk.deskew(st, offsets=offs, origin=0, width=w, out=out,
                                              psum=False, pmax=False, tune="auto"), 20)
     bwd = _b2b_ms(torch, lambda: dsk.backward(st, gd, offs, 0), 20)
-    del st, out, gd
+    del out, gd
+    # calibration: recover 32 deg from 30 deg, the target being the
+    # library's own deskew at 32 deg on the same frame
+    from paper_2211_00645_amd import autograd as ag
+    a32 = torch.tensor(32.0, dtype=torch.float64, device="cuda")
+    tgt = dsk.deskew(st, offsets=ag.offsets_from_angle(a32, n, STEP, PIXEL), origin=0,
+                     width=w, psum=False, pmax=False)["vol"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    angle, hist = ag.calibrate_angle(st, tgt, 30.0, STEP, PIXEL, 0, w)
+    torch.cuda.synchronize()
+    cal_s = time.perf_counter() - t0
+    del st, tgt
     torch.cuda.empty_cache()
     fb = 4 * n * r * c + 4 * n * r * w
     bb = 4 * n * r * w + 4 * n * r * c + 4 * n * r * c
     return {"workload": "float32 256x512x1024, frame 1793",
             "forward_ms": fwd, "forward_gbs": fb / fwd / 1e6,
-            "backward_ms": bwd, "backward_gbs": bb / bwd / 1e6}
+            "backward_ms": bwd, "backward_gbs": bb / bwd / 1e6,
+            "calibration": {"from_deg": 30.0, "target_deg": 32.0, "final_deg": angle,
+                            "steps": len(hist), "seconds": cal_s}}
 
 
 def bench_view(torch, dsk, synth):
@@ -310,7 +373,7 @@ def bench_scaling(torch, dsk, synth):
     return res
 
 
-def bench_serving(torch, dsk, synth, n_req, rate):
+def bench_serving(torch, dsk, synth, n_req, rate, sweep=(), sweep_s=10.0):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time."""
     from paper_2211_00645_amd import serving as sv
@@ -337,6 +400,15 @@ def bench_serving(torch, dsk, synth, n_req, rate):
         log(f"serving {mode}: p50 {res[mode]['latency_p50_ms']:.2f} ms p99 "
             f"{res[mode]['latency_p99_ms']:.2f} ms; plain p99 "
             f"{res[mode + '_plain']['latency_p99_ms']:.2f} ms")
+    if sweep:
+        res["sweep"] = {}
+        for lam in sweep:
+            n = int(max(20, round(lam * sweep_s)))
+            tr = synth.serving_trace(n, lam, 11)
+            sch = sv.Scheduler(ex, budget, n_slots=4, max_batch=8)
+            res["sweep"][f"{lam:g}Hz"] = dict(sv.summarize(sch.run(sv.make_requests(tr))),
+                                               launches=sch.launches)
+            log(f"serving {lam:g} Hz x {n}: p99 {res['sweep'][f'{lam:g}Hz']['latency_p99_ms']:.2f} ms")
     del pool, ex
     torch.cuda.empty_cache()
     return res
@@ -357,6 +429,10 @@ def main():
                          "once before the warm-up) or default (the library default)")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-rate", type=float, default=50.0)
+    ap.add_argument("--serve-sweep", default="",
+                    help="comma list of arrival rates (Hz) to also run live for about "
+                         "--serve-seconds each, e.g. 5,10,20,50")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); this build has no "
@@ -431,11 +507,13 @@ def main():
     cpu = None
     del outs
     torch.cuda.synchronize()
+    config1 = None
     if args.cpu_seconds > 0:
         host = stack.cpu().numpy()
         cpu = cpu_baseline(host, args.cpu_seconds)
         cpu.pop("seconds", None)
         del host
+        config1 = config1_times(torch, dsk, synth)
     del stack
     torch.cuda.empty_cache()
 
@@ -464,7 +542,9 @@ def main():
         ext["scaling"] = bench_scaling(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
-        ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate)
+        ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate,
+                                       [float(v) for v in args.serve_sweep.split(",") if v],
+                                       args.serve_seconds)
 
     rec = {
         "metric": METRIC,
@@ -485,6 +565,7 @@ def main():
                    "input": "u16", "volume": "f32", "sum_accumulation": "f64",
                    "launch_shape": shape or "library default",
                    "parallelism": "single GPU"},
+        "input_voxels_per_s": N * R * C / (ms_per_step * 1e-3),
         "hbm_gbs": alg / (ms_per_step * 1e-3) / 1e9,
         "kernel_ms_avg": avg_kern_ms,
         "kernel_ms_median": statistics.median(kern_ms),
@@ -495,6 +576,8 @@ def main():
         "copy_ceiling_gbs": copy_gbs,
         "cpu_baseline": cpu,
     }
+    if config1 is not None:
+        rec["config1"] = config1
     if "serving" in ext:
         rec["latency_p99_ms_live"] = ext["serving"]["live"]["latency_p99_ms"]
     rec.update(ext)

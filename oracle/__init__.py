@@ -44,6 +44,8 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.orc_threads.restype = ctypes.c_int
     lib.orc_threads.argtypes = []
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
     lib.orc_shift_px.restype = ctypes.c_double
     lib.orc_shift_px.argtypes = [ctypes.c_double] * 3
     lib.orc_offsets_uniform.restype = None
@@ -86,6 +88,11 @@ def _ptr(a, typ):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the oracle's parallel loops (timing only)."""
+    _load().orc_set_threads(int(n))
 
 
 def shift_px(angle_deg: float, step_um: float, pixel_um: float) -> float:

@@ -48,6 +48,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Set the threads the parallel loops use (n >= 1); for timing only. */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* Eq. 1: the lateral shift between consecutive images is l = z cos(alpha),
  * z being the scan distance between images.  Expressed in image pixels of
  * sample-space size p: s = (z * cos(alpha)) / p, alpha given in degrees. */
