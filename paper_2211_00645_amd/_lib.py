@@ -8,7 +8,8 @@ import ctypes
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libdeskew.so")
+# DSK_LIB may name another build of the same library (the host-ASan build)
+LIB_PATH = os.environ.get("DSK_LIB") or os.path.join(_PKG, "libdeskew.so")
 
 c_i32, c_i64, c_dbl, c_vp, c_sz = (ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                    ctypes.c_void_p, ctypes.c_size_t)

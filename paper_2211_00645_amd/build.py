@@ -2,6 +2,12 @@
 
 Each source compiles to an object in parallel, then one link.
 Usage: ``python -m paper_2211_00645_amd.build`` (or call ``build()``).
+
+``--asan`` (``build(asan=True)``) builds ``libdeskew_asan.so`` instead: the
+host code instrumented with AddressSanitizer (every ``-fsanitize=`` flag
+goes to the host pass only; the device code is that of the normal build).
+It is loaded with ``DSK_LIB`` pointing at it and the sanitizer runtime
+preloaded, for host-only checks on a machine without a GPU.
 """
 import os
 import subprocess
@@ -13,6 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdeskew.so")
+LIB_ASAN = os.path.join(PKG, "libdeskew_asan.so")
 SOURCES = ["deskew.hip", "batch.hip", "tune.hip", "rolling.hip", "view.hip", "affine.hip"]
 ARCH = os.environ.get("DSK_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -22,13 +29,19 @@ FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
          "-I", INCLUDE, "-I", CSRC]
 
 
-def build(verbose: bool = False) -> str:
-    objdir = os.path.join(PKG, "_build")
+HOST_ASAN = "-Xarch_host -fsanitize=address -Xarch_host -fno-omit-frame-pointer -Xarch_host -g".split()
+HOST_ASAN_LINK = "-Xarch_host -fsanitize=address -shared-libasan".split()
+
+
+def build(verbose: bool = False, asan: bool = False) -> str:
+    objdir = os.path.join(PKG, "_build", "asan" if asan else "")
     os.makedirs(objdir, exist_ok=True)
+    lib = LIB_ASAN if asan else LIB
+    extra = HOST_ASAN if asan else []
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
-        cmd = ["hipcc"] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = ["hipcc"] + FLAGS + extra + ["-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
@@ -36,13 +49,23 @@ def build(verbose: bool = False) -> str:
 
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         objs = list(ex.map(compile_one, SOURCES))
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    cmd = (["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC"] +
+           (HOST_ASAN_LINK if asan else []) +
+           ["-o", lib + ".tmp"] + objs)
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(lib + ".tmp", lib)
+    return lib
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's AddressSanitizer runtime (to preload), or ''."""
+    out = subprocess.run(["hipcc", "--print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = out.stdout.strip()
+    return path if os.path.isabs(path) and os.path.exists(path) else ""
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, asan="--asan" in sys.argv))
