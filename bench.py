@@ -462,9 +462,9 @@ def main():
 
     if args.tune == "auto":
         log("tuning the launch shape for this frame")
-        tuned = dsk.autotune(stack, ANGLE, STEP, PIXEL, out=outs, reps=8)
+        tuned = dsk.autotune(stack, ANGLE, STEP, PIXEL, out=outs, reps=16)
         shape = tuned["tune"]
-        log(f"launch shape {shape} ({tuned['ms']:.4f} ms upper quartile)")
+        log(f"launch shape {shape} ({tuned['ms']:.4f} ms mean while tuning)")
     elif args.tune == "default":
         shape = None
     else:

@@ -150,8 +150,8 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
  * and over).  Times candidate shapes -- one or two 4-column groups per
  * lane, unpaced and paced at 5000-6000 GB/s, and the default -- each `reps`
  * times (3..64) round-robin after one untimed round, on the caller's own
- * buffers and stream, and returns in *tune the shape with the lowest
- * upper-quartile time (*ms, host, may be NULL).  Arguments as
+ * buffers and stream, and returns in *tune the shape with the lowest mean
+ * time over its launches but the slowest (*ms, host, may be NULL).  Arguments as
  * dsk_deskew_offsets_tuned.  Every trial computes the full result, so the
  * outputs may be written (with the correct values) or, when the choice is
  * already known, left untouched: call the forward with *tune afterwards.

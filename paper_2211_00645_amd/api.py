@@ -135,7 +135,7 @@ def autotune(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *
 
     Arguments as :func:`deskew`.  Times the library's candidate shapes
     (pacing rate, columns per lane) on this stack and returns
-    ``{"tune": shape dict, "ms": upper-quartile time}``; the choice is
+    ``{"tune": shape dict, "ms": mean time}``; the choice is
     remembered per frame (and in the ``DSK_TUNE_CACHE`` file when that
     variable is set), so later calls return at once.  Pass the shape as
     ``deskew(..., tune=...)``, or call ``deskew(..., tune="auto")``.

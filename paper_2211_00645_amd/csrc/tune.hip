@@ -146,8 +146,10 @@ std::map<std::string, std::pair<dsk_tune, double>> g_memo;
 
 // Times every candidate `reps` times, round-robin (one launch of each per
 // round, so slow drifts of the device touch all alike), after one untimed
-// round.  Score: the upper-quartile time, so a shape that is fast only some
-// of the time (a pace at the cliff's edge) loses to one that is steady.
+// round.  Score: the mean time without the single slowest launch, so a pace
+// at the cliff's edge that falls behind now and then pays for those
+// launches (the throughput of back-to-back launches is their mean), while
+// one launch slowed by something else does not decide.
 int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in, int in_is_f32,
                     dsk_dims d, const double *offs, double shift, int64_t origin, float *vol,
                     float *psum, float *pmax, int64_t width, hipStream_t s,
@@ -178,7 +180,9 @@ int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in,
     score->assign(nc, 0.0);
     for (size_t i = 0; i < nc; ++i) {
         std::sort(t[i].begin(), t[i].end());
-        (*score)[i] = t[i][(size_t)(3 * reps) / 4];
+        double sum = 0.0;
+        for (size_t k = 0; k + 1 < t[i].size(); ++k) sum += t[i][k];
+        (*score)[i] = sum / (double)(t[i].size() - 1);
     }
     return DSK_OK;
 }
