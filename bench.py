@@ -339,8 +339,16 @@ def bench_rolling(torch, dsk, synth):
         def one():
             rv.update(k[0] % n, st[k[0] % n])
             k[0] += 1
-        ms = _median_ms(torch, one, 50)
-        res[name] = {"ms_per_image": ms, "images_per_s": 1e3 / ms, "width": rv.width}
+        ms = _median_ms(torch, one, 50)          # one call, host launch included
+        kms = _b2b_ms(torch, one, 100)           # calls back to back
+        # bytes per update: the image, the leaf read and written, the FP64
+        # running sum read and written, both projections written, and per
+        # tree level a sibling read and the parent written
+        levels = max(1, math.ceil(math.log2(n))) if n > 1 else 0
+        w = rv.width
+        alg = 2 * r * c + (8 + 16 + 8 + 8 * levels) * r * w
+        res[name] = {"ms_per_image": ms, "images_per_s": 1e3 / ms, "width": w,
+                     "kernel_ms": kms, "algorithmic_bytes": alg, "gbs": alg / kms / 1e6}
         del rv, st
         torch.cuda.empty_cache()
     return res
