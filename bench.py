@@ -186,17 +186,17 @@ def _one_ms(torch, fn):
     return e0.elapsed_time(e1)
 
 
-def bench_batch(torch, dsk, synth):
-    """64 ragged uint16 stacks: one persistent launch (graph replay) against
-    64 plain launches on one stream.  Both write the same output buffers
-    (where outputs sit in memory moves this workload's time by up to 20%, so
-    the two are compared on one placement) and are timed alternately."""
+def _batch_case(torch, dsk, synth, jobs, seed0, label):
+    """One graph launch of a ragged batch against the same stacks as plain
+    launches on one stream.  Both write the same output buffers (where
+    outputs sit in memory moves this workload's time by up to 20%, so the
+    two are compared on one placement) and are timed alternately."""
     from paper_2211_00645_amd.batch import Batch
-    jobs = synth.ragged_jobs(64, seed=0)
     stacks, geoms = [], []
     for i, j in enumerate(jobs):
         shp = (j["planes"], j["rows"], j["cols"])
-        stacks.append(synth.blob_stack(shp, synth.blobs_for_volume(*shp), 1000 + i, device="cuda"))
+        stacks.append(synth.blob_stack(shp, synth.blobs_for_volume(*shp), seed0 + i,
+                                       device="cuda"))
         geoms.append((j["angle_deg"], j["step_um"], j["pixel_um"]))
     torch.cuda.synchronize()
     b = Batch(stacks, geoms)
@@ -227,14 +227,27 @@ def bench_batch(torch, dsk, synth):
     b.close()
     del b, outs, stacks
     torch.cuda.empty_cache()
-    return {"workload": "64 ragged uint16 stacks (planes 50-400, rows 256/512/1024, "
-                        "cols 512-2048, 30/35/45 deg), seed 0",
-            "graph_ms": ms_graph, "plain_64_launches_ms": ms_plain,
+    return {"workload": label,
+            "graph_ms": ms_graph, "plain_launches_ms": ms_plain,
             "speedup": ms_plain / ms_graph, "gbs_graph": alg / ms_graph / 1e6,
             "voxels_per_s_graph": vox / ms_graph * 1e3, "algorithmic_bytes": alg,
             "bitwise_equal": same, "mode": mode, "tune": tune,
             "timing": "graph replays and plain launch sequences alternate, 6 each, on the "
                       "same output buffers; medians"}
+
+
+def bench_batch(torch, dsk, synth):
+    """The 64-stack ragged batch (planes 50-400, rows 256/512/1024, cols
+    512-2048), and 256 small ragged stacks (the same draw scaled by 1/8)
+    where each plain launch is short and launch overhead counts."""
+    big = _batch_case(torch, dsk, synth, synth.ragged_jobs(64, seed=0), 1000,
+                      "64 ragged uint16 stacks (planes 50-400, rows 256/512/1024, "
+                      "cols 512-2048, 30/35/45 deg), seed 0")
+    small = _batch_case(torch, dsk, synth, synth.ragged_jobs(256, seed=1, scale=0.125), 5000,
+                        "256 small ragged uint16 stacks (the same draw scaled by 1/8: planes "
+                        "7-50, rows 32/64/128, cols 64-256), seed 1")
+    big["small_stacks"] = small
+    return big
 
 
 def _b2b_ms(torch, fn, reps):
@@ -530,8 +543,10 @@ def main():
     if "batch" in extras:
         log("batch: 64 ragged stacks")
         ext["batch"] = bench_batch(torch, dsk, synth)
-        log(f"batch: graph {ext['batch']['graph_ms']:.2f} ms vs plain "
-            f"{ext['batch']['plain_64_launches_ms']:.2f} ms")
+        bb, bs = ext["batch"], ext["batch"]["small_stacks"]
+        log(f"batch: graph {bb['graph_ms']:.2f} ms ({bb['mode']}) vs plain "
+            f"{bb['plain_launches_ms']:.2f} ms; small stacks: graph {bs['graph_ms']:.3f} ms "
+            f"({bs['mode']}) vs plain {bs['plain_launches_ms']:.3f} ms")
     if "autograd" in extras:
         log("autograd: forward + backward")
         ext["autograd"] = bench_autograd(torch, dsk, synth)

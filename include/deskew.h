@@ -206,13 +206,15 @@ int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims d,
  * workgroup per compute-unit slot walks a shared list of (stack, row,
  * column-tile) items: no per-launch tails, best for many small stacks) or
  * one plain paced launch per job (each job's wavefronts keep to one
- * schedule: best for large stacks), whichever the autotuner measures
- * faster.  Each job's outputs are bitwise identical to its own
+ * schedule: best for large stacks), in the default shape or in each job
+ * frame's tuned shape, whichever the autotuner measures faster.  Each job's outputs are bitwise identical to its own
  * dsk_deskew_offsets_u16 / dsk_deskew_u16 call in either mode.
  * ------------------------------------------------------------------- */
 enum {
-    DSK_BATCH_PERSISTENT = 0,  /* one persistent kernel over all jobs */
-    DSK_BATCH_PER_JOB = 1      /* one plain launch per job */
+    DSK_BATCH_PERSISTENT = 0,   /* one persistent kernel over all jobs */
+    DSK_BATCH_PER_JOB = 1,      /* one plain launch per job, default shape */
+    DSK_BATCH_PER_JOB_TUNED = 2 /* one plain launch per job, in the shape
+                                   dsk_deskew_autotune picks for its frame */
 };
 
 typedef struct {
@@ -230,11 +232,12 @@ typedef struct dsk_batch dsk_batch;
 /* Build a batch: validates the jobs, uploads the job table (device memory
  * owned by the batch), picks the execution (tune != NULL: the persistent
  * kernel in that shape; NULL: time the persistent kernel's candidate shapes
- * and the per-job mode on `stream` -- which runs the jobs, so outputs are
- * then already written -- and keep the fastest, remembered per batch shape
- * class in the DSK_TUNE_CACHE file when that variable is set), and captures
- * the launch in a HIP graph.  Host call; allocates and synchronises
- * `stream`. */
+ * and the two per-job modes on `stream` -- which runs the jobs, so outputs
+ * are then already written; the tuned per-job mode first tunes each job's
+ * frame with dsk_deskew_autotune -- and keep the fastest, remembered per
+ * batch shape class in the DSK_TUNE_CACHE file when that variable is set),
+ * and captures the launch in a HIP graph.  Host call; allocates and
+ * synchronises `stream`. */
 int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune *tune,
                      hipStream_t stream, dsk_batch **out);
 
@@ -248,8 +251,8 @@ int dsk_batch_launch_direct(dsk_batch *batch, hipStream_t stream);
  * 0 when the shape was given). */
 int dsk_batch_get_tune(const dsk_batch *batch, dsk_tune *tune, double *ms);
 
-/* The execution mode the batch uses (DSK_BATCH_PERSISTENT or
- * DSK_BATCH_PER_JOB) into *mode (host). */
+/* The execution mode the batch uses (DSK_BATCH_PERSISTENT,
+ * DSK_BATCH_PER_JOB or DSK_BATCH_PER_JOB_TUNED) into *mode (host). */
 int dsk_batch_get_mode(const dsk_batch *batch, int *mode);
 
 int dsk_batch_destroy(dsk_batch *batch);

@@ -2,11 +2,12 @@
 deskewed by ONE graph launch.
 
 The graph holds either one persistent kernel over all jobs or one plain
-paced launch per job.  The library's autotuner times the persistent
-kernel's candidate shapes (threads per workgroup, columns per thread, plane
-unroll, pacing) and the per-job mode on the batch's own buffers, keeps the
-fastest, and caches the choice per device architecture and batch shape
-class in a JSON file (``DSK_TUNE_CACHE``).  Each job's outputs are bitwise
+paced launch per job (default shape, or each job frame's tuned shape).  The
+library's autotuner times the persistent kernel's candidate shapes (threads
+per workgroup, columns per thread, plane unroll, pacing) and the per-job
+modes on the batch's own buffers, keeps the fastest, and caches the choice
+per device architecture and batch shape class in a JSON file
+(``DSK_TUNE_CACHE``).  Each job's outputs are bitwise
 identical to its own single-stack call in either mode.
 """
 from __future__ import annotations
@@ -96,12 +97,13 @@ class Batch:
 
     @property
     def mode(self):
-        """"persistent" (one kernel over all jobs) or "per_job" (one plain
-        launch per job), as the autotuner chose (persistent when a shape
-        was given)."""
+        """"persistent" (one kernel over all jobs), "per_job" (one plain
+        launch per job, default shape) or "per_job_tuned" (one plain launch
+        per job in its frame's tuned shape), as the autotuner chose
+        (persistent when a shape was given)."""
         m = ctypes.c_int()
         L.check(L.lib().dsk_batch_get_mode(self._h, ctypes.byref(m)), "dsk_batch_get_mode")
-        return "per_job" if m.value == 1 else "persistent"
+        return {0: "persistent", 1: "per_job", 2: "per_job_tuned"}[m.value]
 
     def launch(self, stream=None, graph=True):
         """Enqueue the whole batch (graph replay, or a direct launch)."""

@@ -24,6 +24,7 @@ struct dsk_batch {
     int n_jobs = 0;
     std::vector<dsk_job> jobs;
     int mode = DSK_BATCH_PERSISTENT;
+    std::vector<dsk_tune> job_tunes;     // per-job shapes (DSK_BATCH_PER_JOB_TUNED)
     dsk_tune tune{};
     double best_ms = 0.0;
     int64_t total_tiles = 0;
@@ -193,25 +194,43 @@ int time_shape(dsk_batch *bt, const dsk_tune &t, hipStream_t s, int reps, double
     return DSK_OK;
 }
 
-// Per-job mode: every job as its own plain launch in the library default
-// shape (paced, so each job's wavefronts keep to one schedule).
-int launch_per_job(const dsk_batch *bt, hipStream_t s) {
-    for (const dsk_job &j : bt->jobs) {
+// Per-job modes: every job as its own plain launch (paced, so each job's
+// wavefronts keep to one schedule), in the library default shape or in the
+// shape the single-stack tuner picks for the job's frame.
+int launch_per_job(const dsk_batch *bt, bool tuned, hipStream_t s) {
+    for (size_t i = 0; i < bt->jobs.size(); ++i) {
+        const dsk_job &j = bt->jobs[i];
+        const dsk_tune &t = tuned ? bt->job_tunes[i] : kDefaultTune;
         const int st = launch_forward(j.in, 0, j.dims, j.offsets_dev, j.shift_px, j.origin, j.vol,
-                                      j.psum, j.pmax, j.out_width, kDefaultTune, s);
+                                      j.psum, j.pmax, j.out_width, t, s);
+        if (st != DSK_OK) return st;
+    }
+    return DSK_OK;
+}
+
+// The tuner's shape for every job's frame (remembered per frame, so jobs of
+// one frame and later batches of it tune once).
+int tune_jobs(dsk_batch *bt, hipStream_t s) {
+    bt->job_tunes.assign(bt->jobs.size(), kDefaultTune);
+    for (size_t i = 0; i < bt->jobs.size(); ++i) {
+        const dsk_job &j = bt->jobs[i];
+        const int st = dsk_deskew_autotune(j.in, 0, j.dims, j.offsets_dev, j.shift_px, j.origin,
+                                           j.vol, j.psum, j.pmax, j.out_width, 3, s,
+                                           &bt->job_tunes[i], nullptr);
         if (st != DSK_OK) return st;
     }
     return DSK_OK;
 }
 
 int launch_mode(dsk_batch *bt, hipStream_t s) {
-    if (bt->mode == DSK_BATCH_PER_JOB) return launch_per_job(bt, s);
+    if (bt->mode == DSK_BATCH_PER_JOB) return launch_per_job(bt, false, s);
+    if (bt->mode == DSK_BATCH_PER_JOB_TUNED) return launch_per_job(bt, true, s);
     return hip_status(
         launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, bt->tune, s));
 }
 
-// Best of `reps` timed runs (ms) of the per-job mode, after one untimed run.
-int time_per_job(dsk_batch *bt, hipStream_t s, int reps, double *ms) {
+// Best of `reps` timed runs (ms) of a per-job mode, after one untimed run.
+int time_per_job(dsk_batch *bt, bool tuned, hipStream_t s, int reps, double *ms) {
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess) return DSK_EHIP;
     if (hipEventCreate(&b) != hipSuccess) {
@@ -219,10 +238,10 @@ int time_per_job(dsk_batch *bt, hipStream_t s, int reps, double *ms) {
         return DSK_EHIP;
     }
     double best = 1e300;
-    int st = launch_per_job(bt, s);
+    int st = launch_per_job(bt, tuned, s);
     for (int i = 0; i < reps && st == DSK_OK; ++i) {
         if (hipEventRecord(a, s) != hipSuccess) st = DSK_EHIP;
-        if (st == DSK_OK) st = launch_per_job(bt, s);
+        if (st == DSK_OK) st = launch_per_job(bt, tuned, s);
         if (st == DSK_OK && hipEventRecord(b, s) != hipSuccess) st = DSK_EHIP;
         if (st == DSK_OK && hipEventSynchronize(b) != hipSuccess) st = DSK_EHIP;
         float f = 0.0f;
@@ -280,13 +299,21 @@ extern "C" int dsk_batch_create(const dsk_job *jobs, int n_jobs, const dsk_tune 
                 }
             }
             double m = 0.0;
-            if (st == DSK_OK) st = time_per_job(bt, stream, 2, &m);
+            if (st == DSK_OK) st = time_per_job(bt, false, stream, 2, &m);
             if (st == DSK_OK && m < best) {
                 best = m;
                 mode = DSK_BATCH_PER_JOB;
             }
+            if (st == DSK_OK) st = tune_jobs(bt, stream);
+            if (st == DSK_OK) st = time_per_job(bt, true, stream, 2, &m);
+            if (st == DSK_OK && m < best) {
+                best = m;
+                mode = DSK_BATCH_PER_JOB_TUNED;
+            }
             ms = best;
             if (st == DSK_OK) tune_cache_store(key, t, ms, mode);
+        } else if (mode == DSK_BATCH_PER_JOB_TUNED) {
+            st = tune_jobs(bt, stream);
         }
         bt->tune = t;
         bt->best_ms = ms;

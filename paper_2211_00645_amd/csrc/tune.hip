@@ -58,7 +58,7 @@ bool tune_cache_lookup(const std::string &key, dsk_tune *t, double *ms, int *mod
             "\"unroll\": %d, \"wg_per_cu\": %d, \"pace_gbs\": %d, \"ms\": %lf, \"mode\": %d}",
             k, &c.block, &c.per_thread, &c.nt_store, &c.unroll, &c.wg_per_cu, &c.pace_gbs, &m,
             &md);
-        if (got >= 8 && key == k && tune_ok(c) && md >= 0 && md <= 1) {
+        if (got >= 8 && key == k && tune_ok(c) && md >= 0 && md <= 2) {
             *t = c;
             *ms = m;
             if (mode) *mode = got == 9 ? md : 0;

@@ -50,8 +50,10 @@ def test_graph_replays_match_single_launches(small, tmp_path):
     t = b.tune
     _say(f"batch: tuned shape {t}")
     assert t["tuned_ms"] > 0
-    entries = json.loads(cache.read_text())
-    assert len(entries) == 1
+    # one entry for the batch's shape class (and one per job frame the
+    # tuned per-job mode measured)
+    batch_keys = [k for k in json.loads(cache.read_text()) if "/jobs" in k]
+    assert len(batch_keys) == 1
     solo = [_solo(s, g) for s, g in zip(stacks, geoms)]
     for rep in range(3):
         for o in b.outputs:
@@ -77,27 +79,31 @@ def test_graph_replays_match_single_launches(small, tmp_path):
         assert torch.equal(o["vol"], s["vol"])
     b.close()
     b2.close()
-    # the remembered choice decides the mode: flip it, and the other mode's
-    # graph gives the same bits replay after replay
-    (key, ent), = json.loads(cache.read_text()).items()
-    other = "per_job" if mode == "persistent" else "persistent"
-    ent["mode"] = 1 if other == "per_job" else 0
-    cache.write_text("{\n" + f'  "{key}": ' + json.dumps(ent) + "\n}\n")
-    b3 = Batch(stacks, geoms, cache_path=cache)
-    _say(f"batch: forced mode {other}")
-    assert b3.mode == other
-    for rep in range(2):
-        for o in b3.outputs:
-            for k in ("vol", "psum", "pmax"):
-                o[k].fill_(-1.0)
-        b3.launch()
-        junk = torch.randn(1 << 20, device=DEV).sum()
-        torch.cuda.synchronize()
-        for i, (o, s) in enumerate(zip(b3.outputs, solo)):
-            for k in ("vol", "psum", "pmax"):
-                assert torch.equal(o[k], s[k]), (other, rep, i, k)
-        del junk
-    b3.close()
+    # the remembered choice decides the mode: set each of the others, and
+    # its graph gives the same bits replay after replay
+    entries = json.loads(cache.read_text())
+    key = batch_keys[0]
+    ent = entries[key]
+    codes = {"persistent": 0, "per_job": 1, "per_job_tuned": 2}
+    for other in [m for m in codes if m != mode]:
+        ent["mode"] = codes[other]
+        cache.write_text("{\n" + ",\n".join(f'  "{k}": ' + json.dumps(v)
+                                             for k, v in entries.items()) + "\n}\n")
+        b3 = Batch(stacks, geoms, cache_path=cache)
+        _say(f"batch: forced mode {other}")
+        assert b3.mode == other
+        for rep in range(2):
+            for o in b3.outputs:
+                for k in ("vol", "psum", "pmax"):
+                    o[k].fill_(-1.0)
+            b3.launch()
+            junk = torch.randn(1 << 20, device=DEV).sum()
+            torch.cuda.synchronize()
+            for i, (o, s) in enumerate(zip(b3.outputs, solo)):
+                for k in ("vol", "psum", "pmax"):
+                    assert torch.equal(o[k], s[k]), (other, rep, i, k)
+            del junk
+        b3.close()
 
 
 @pytest.mark.parametrize("tune", [dict(block=64, per_thread=4, unroll=1, nt_store=0),
