@@ -22,6 +22,8 @@ is tested on the CPU with a fake clock and a mock executor.
 """
 from __future__ import annotations
 
+import contextlib
+import gc
 import math
 import time
 from collections import deque
@@ -118,6 +120,10 @@ class Scheduler:
         self.space_waits = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
+        with gc_paused():
+            return self._run(requests)
+
+    def _run(self, requests: List[Request]) -> List[Request]:
         arrivals = sorted(requests, key=lambda r: r.t_arrival)
         for r in arrivals:
             r.width = self.ex.width(r)
@@ -205,9 +211,33 @@ class Scheduler:
         return done
 
 
+@contextlib.contextmanager
+def gc_paused():
+    """Pause Python's cyclic garbage collector for a serving loop (reference
+    counting still frees every request's objects at once): a collection
+    pass over a large heap can stall the loop for tens of milliseconds and
+    land inside a request's latency.  One collection runs before the loop
+    starts; the previous setting is restored, and one collection runs, on
+    exit."""
+    was = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+            gc.collect()
+
+
 def run_plain(executor, requests: List[Request], clock=None) -> List[Request]:
     """Baseline: one stack at a time in arrival order, each waited for
     before the next starts (no overlap, no batching)."""
+    with gc_paused():
+        return _run_plain(executor, requests, clock)
+
+
+def _run_plain(executor, requests: List[Request], clock=None) -> List[Request]:
     clock = clock or RealClock()
     out = []
     for r in sorted(requests, key=lambda q: q.t_arrival):

@@ -152,3 +152,22 @@ def test_fragmented_executor_memory_requeues_batch():
     # FIFO order of admission is kept across the requeues
     flat = [rid for b in ex.submitted for rid in b]
     assert sorted(set(flat)) == list(range(80))
+
+
+def test_scheduler_pauses_and_restores_the_cyclic_collector():
+    import gc
+    seen = []
+
+    class Probe(MockExecutor):
+        def submit(self, slot, reqs):
+            seen.append(gc.isenabled())
+            return super().submit(slot, reqs)
+
+    clock = FakeClock()
+    ex = Probe(clock, s_per_byte=1e-9)
+    was = gc.isenabled()
+    done = Scheduler(ex, budget_bytes=1 << 40, n_slots=2, clock=clock).run(
+        _reqs([0.0, 0.01, 0.02, 0.03]))
+    assert [r.status for r in done] == ["done"] * 4
+    assert seen and not any(seen)
+    assert gc.isenabled() == was
