@@ -562,7 +562,7 @@ def main():
         ext["rolling"] = bench_rolling(torch, dsk, synth)
     if "scaling" in extras:
         log("scaling: time vs images and width")
-        ext["scaling"] = bench_scaling(torch, dsk, synth)
+        ext["size_sweep"] = bench_scaling(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate,
@@ -603,6 +603,8 @@ def main():
         rec["config1"] = config1
     if "serving" in ext:
         rec["latency_p99_ms_live"] = ext["serving"]["live"]["latency_p99_ms"]
+    # the extras never replace a field of the line's contract
+    assert not set(ext) & set(rec), sorted(set(ext) & set(rec))
     rec.update(ext)
     print(json.dumps(rec), flush=True)
 

@@ -148,10 +148,12 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
 
 /* Launch-shape tuner for one frame (the shape a live stream deskews over
  * and over).  Times candidate shapes -- one or two 4-column groups per
- * lane, unpaced and paced at 5000-6000 GB/s, and the default -- each `reps`
- * times (3..64) round-robin after one untimed round, on the caller's own
- * buffers and stream, and returns in *tune the shape with the lowest mean
- * time over its launches but the slowest (*ms, host, may be NULL).  Arguments as
+ * lane, unpaced and paced at 5000-6000 GB/s, and the default -- for `reps`
+ * rounds (3..64), a burst of 3 back-to-back launches of each shape per
+ * round, round-robin after one untimed round, on the caller's own buffers
+ * and stream, and returns in *tune, among the shapes whose mean time per
+ * launch is within 0.5% of the fastest, the one paced slowest (*ms, host,
+ * may be NULL: its mean time).  Arguments as
  * dsk_deskew_offsets_tuned.  Every trial computes the full result, so the
  * outputs may be written (with the correct values) or, when the choice is
  * already known, left untouched: call the forward with *tune afterwards.

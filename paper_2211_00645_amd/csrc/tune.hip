@@ -144,12 +144,14 @@ std::string fwd_key(int in_is_f32, dsk_dims d, int64_t width, bool offs, const f
 std::mutex g_memo_mu;
 std::map<std::string, std::pair<dsk_tune, double>> g_memo;
 
-// Times every candidate `reps` times, round-robin (one launch of each per
-// round, so slow drifts of the device touch all alike), after one untimed
-// round.  Score: the mean time without the single slowest launch, so a pace
-// at the cliff's edge that falls behind now and then pays for those
-// launches (the throughput of back-to-back launches is their mean), while
-// one launch slowed by something else does not decide.
+// Times every candidate `reps` times, round-robin (a burst of kBurst
+// back-to-back launches of each per round, so slow drifts of the device
+// touch all alike, and each is timed the way a stream of stacks runs it),
+// after one untimed round.  Score: the mean time per launch over all
+// rounds -- back-to-back throughput -- so a pace at the cliff's edge that
+// falls behind now and then pays for those launches.
+constexpr int kBurst = 3;
+
 int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in, int in_is_f32,
                     dsk_dims d, const double *offs, double shift, int64_t origin, float *vol,
                     float *psum, float *pmax, int64_t width, hipStream_t s,
@@ -159,32 +161,44 @@ int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in,
     int st = DSK_OK;
     for (size_t i = 0; i <= nc && st == DSK_OK; ++i)
         if (hipEventCreate(&ev[i]) != hipSuccess) st = DSK_EHIP;
-    std::vector<std::vector<float>> t(nc);
+    std::vector<double> sum(nc, 0.0);
     for (int round = 0; round <= reps && st == DSK_OK; ++round) {
         if (hipEventRecord(ev[0], s) != hipSuccess) st = DSK_EHIP;
         for (size_t i = 0; i < nc && st == DSK_OK; ++i) {
-            st = launch_forward(in, in_is_f32, d, offs, shift, origin, vol, psum, pmax, width,
-                                cand[i], s);
+            for (int k = 0; k < kBurst && st == DSK_OK; ++k)
+                st = launch_forward(in, in_is_f32, d, offs, shift, origin, vol, psum, pmax,
+                                    width, cand[i], s);
             if (st == DSK_OK && hipEventRecord(ev[i + 1], s) != hipSuccess) st = DSK_EHIP;
         }
         if (st == DSK_OK && hipEventSynchronize(ev[nc]) != hipSuccess) st = DSK_EHIP;
         for (size_t i = 0; i < nc && st == DSK_OK && round > 0; ++i) {
             float ms = 0.0f;
             if (hipEventElapsedTime(&ms, ev[i], ev[i + 1]) != hipSuccess) st = DSK_EHIP;
-            t[i].push_back(ms);
+            sum[i] += ms / kBurst;
         }
     }
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     if (st != DSK_OK) return st;
     score->assign(nc, 0.0);
-    for (size_t i = 0; i < nc; ++i) {
-        std::sort(t[i].begin(), t[i].end());
-        double sum = 0.0;
-        for (size_t k = 0; k + 1 < t[i].size(); ++k) sum += t[i][k];
-        (*score)[i] = sum / (double)(t[i].size() - 1);
-    }
+    for (size_t i = 0; i < nc; ++i) (*score)[i] = sum[i] / reps;
     return DSK_OK;
+}
+
+// The choice: among the candidates within kMargin of the fastest, the one
+// paced slowest (unpaced first) -- the cliff lies just above the fastest
+// pace, and a gain inside the timing noise is not worth standing on its
+// edge.
+constexpr double kMargin = 1.005;
+
+size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &score) {
+    size_t best = 0;
+    for (size_t i = 1; i < cand.size(); ++i)
+        if (score[i] < score[best]) best = i;
+    size_t pick = best;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (score[i] <= score[best] * kMargin && cand[i].pace_gbs < cand[pick].pace_gbs) pick = i;
+    return pick;
 }
 
 }  // namespace
@@ -216,9 +230,7 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
                                        shift_px, origin, vol, psum, pmax, out_width, stream,
                                        &score);
         if (st != DSK_OK) return st;
-        size_t bi = 0;
-        for (size_t i = 1; i < cand.size(); ++i)
-            if (score[i] < score[bi]) bi = i;
+        const size_t bi = choose(cand, score);
         best = cand[bi];
         best_ms = score[bi];
         tune_cache_store(key, best, best_ms, 0);

@@ -56,3 +56,15 @@ def test_entry_module_has_build_and_smoke():
     sys.path.insert(0, ROOT)
     import __graft_entry__ as g
     assert callable(g.build) and callable(g.smoke)
+
+
+def test_extras_keys_never_shadow_the_line_contract():
+    """Every extra measurement lands under its own key; none may replace a
+    field the one-line contract defines (metric, value, scaling, ...)."""
+    import re
+    src = open(os.path.join(ROOT, "bench.py")).read()
+    extra_keys = set(re.findall(r'ext\["(\w+)"\]\s*=', src))
+    contract = {"metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step",
+                "higher_is_better", "scaling", "vs_baseline", "dtype", "data", "config",
+                "roofline", "cpu_baseline"}
+    assert extra_keys and not extra_keys & contract, extra_keys & contract
