@@ -367,7 +367,7 @@ def bench_rolling(torch, dsk, synth):
     return res
 
 
-def bench_scaling(torch, dsk, synth):
+def bench_size_sweep(torch, dsk, synth):
     """Forward time against the number of images N (512 x 2048 images at
     35 deg) and against the output width W (512 images, scan step varied):
     the paper's processing time grows linearly in both (Supp. Table 1).
@@ -445,9 +445,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,scaling,serving",
+    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,sizes,serving",
                     help="comma list of extra measurements (batch, autograd, view, affine, "
-                         "rolling, scaling, serving) or none")
+                         "rolling, sizes, serving) or none")
     ap.add_argument("--tune", default="auto",
                     help="launch shape of the timed forward: auto (the library's tuner, run "
                          "once before the warm-up) or default (the library default)")
@@ -565,9 +565,9 @@ def main():
     if "rolling" in extras:
         log("rolling: per-image update")
         ext["rolling"] = bench_rolling(torch, dsk, synth)
-    if "scaling" in extras:
-        log("scaling: time vs images and width")
-        ext["size_sweep"] = bench_scaling(torch, dsk, synth)
+    if "sizes" in extras:
+        log("size sweep: time vs images and width")
+        ext["size_sweep"] = bench_size_sweep(torch, dsk, synth)
     if "serving" in extras:
         log("serving")
         ext["serving"] = bench_serving(torch, dsk, synth, args.serve_requests, args.serve_rate,
