@@ -223,14 +223,22 @@ def test_clipped_and_padded_width_and_projection_only(cfg1):
 
 def test_live_scale_config2_sampled_rows():
     """512 x 512 x 2048 uint16 at 35 deg: every output of sampled rows, in the
-    launch configuration the benchmark times."""
+    launch configuration the benchmark times (the tuner's shape for this
+    frame), and the whole result bitwise equal to the default shape's."""
     _say("forward: config 2 (512x512x2048), generating")
     st = synth.blob_stack((512, 512, 2048), 2000, 2, device=DEV)
     torch.cuda.synchronize()
-    _say("forward: config 2 deskew")
-    out = dsk.deskew(st, 35.0, 0.4, 0.115)
+    _say("forward: config 2 deskew, tuned shape")
+    out = dsk.deskew(st, 35.0, 0.4, 0.115, tune="auto")
     torch.cuda.synchronize()
     assert out["width"] == 3504 and out["origin"] == 0
+    _say("forward: config 2 deskew, default shape")
+    dflt = dsk.deskew(st, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(out[k], dflt[k]), k
+    del dflt
+    torch.cuda.empty_cache()
     rows = [0, 1, 137, 255, 256, 400, 511]
     sn = st.cpu().numpy()
     off = oracle.offsets_uniform(512, oracle.shift_px(35.0, 0.4, 0.115))
