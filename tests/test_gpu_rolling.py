@@ -71,3 +71,32 @@ def test_paper_display_shape(n):
     rv.reset()
     torch.cuda.synchronize()
     assert not rv.pmax.any() and not rv.vol.any()
+
+
+def test_full_stack_512x512x2048():
+    """The benchmark stack's shape, updated image by image in order and then
+    with a few images replaced: bitwise the fused deskew of the stack the
+    display holds (the running FP64 sum of an in-order build equals the
+    plane-ordered sum)."""
+    st = synth.blob_stack((512, 512, 2048), 2000, 2, device=DEV)
+    rv = RollingView(512, 512, 2048, 35.0, 0.4, 0.115)
+    for n in range(512):
+        rv.update(n, st[n])
+    ref = dsk.deskew(st, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    assert rv.width == ref["width"] == 3504
+    assert torch.equal(rv.vol, ref["vol"])
+    assert torch.equal(rv.pmax, ref["pmax"])
+    assert torch.equal(rv.psum, ref["psum"])
+    del ref
+    # replace three images by other ones
+    alt = synth.blob_stack((3, 512, 2048), 40, 9, device=DEV)
+    cur = st.clone()
+    for i, n in enumerate((0, 255, 511)):
+        rv.update(n, alt[i])
+        cur[n] = alt[i]
+    ref = dsk.deskew(cur, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    assert torch.equal(rv.vol, ref["vol"])
+    assert torch.equal(rv.pmax, ref["pmax"])
+    torch.testing.assert_close(rv.psum, ref["psum"], rtol=1e-6, atol=0)
