@@ -114,3 +114,33 @@ def test_failed_submit_returns_its_arena_block(pool):
     assert status[2] == "failed"
     assert all(st == "done" for rid, st in status.items() if rid != 2)
     assert ex.arena.used == 0 and sch.used == 0
+
+
+def test_full_size_burst_projections_equal_solo_runs():
+    """The serving workload's sizes (2-channel stacks, 100-400 planes of
+    512/1024 x 1024/2048): the first 16 requests of the benchmark's burst
+    trace, batched through the scheduler with outputs in an arena, return
+    projections bitwise equal to each channel's solo deskew."""
+    from paper_2211_00645_amd import serving as sv
+    big = {}
+    for k, (r, c) in enumerate([(512, 1024), (512, 2048), (1024, 1024), (1024, 2048)]):
+        for ch in range(2):
+            big[(r, c, ch)] = synth.blob_stack((400, r, c), synth.blobs_for_volume(400, r, c),
+                                               500 + 2 * k + ch, device=DEV)
+    torch.cuda.synchronize()
+    reqs = sv.make_requests(synth.serving_trace(16, 1e9, 7))
+    ex = GPUExecutor(big, n_slots=4, arena_bytes=64 << 30)
+    sch = Scheduler(ex, budget_bytes=64 << 30, n_slots=4, max_batch=8)
+    done = sch.run(reqs)
+    print(f"full-size burst: launches={sch.launches}", flush=True)
+    assert all(r.status == "done" for r in done)
+    assert ex.arena.used == 0
+    for r in done:
+        for ch in range(2):
+            solo = dsk.deskew(big[(r.rows, r.cols, ch)][:r.planes], r.angle_deg, r.step_um,
+                              r.pixel_um, vol=False)
+            torch.cuda.synchronize()
+            assert torch.equal(r.result[ch]["psum"], solo["psum"].cpu()), (r.rid, ch)
+            assert torch.equal(r.result[ch]["pmax"], solo["pmax"].cpu()), (r.rid, ch)
+    del big, ex
+    torch.cuda.empty_cache()
