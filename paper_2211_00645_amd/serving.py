@@ -104,7 +104,7 @@ class Scheduler:
     """Admission by memory budget, launch slots, continuous batching."""
 
     def __init__(self, executor, budget_bytes: int, n_slots: int = 4, max_batch: int = 8,
-                 clock=None, keep_volume: bool = True):
+                 clock=None, keep_volume: bool = True, on_complete=None):
         if n_slots < 1 or max_batch < 1:
             raise ValueError("need at least one slot and one request per batch")
         self.ex = executor
@@ -113,6 +113,9 @@ class Scheduler:
         self.max_batch = max_batch
         self.clock = clock or RealClock()
         self.keep_volume = keep_volume
+        # called with each request as it completes (a live display draws its
+        # projections here and lets them go)
+        self.on_complete = on_complete
         self.used = 0
         self.peak_used = 0
         self.launches = 0
@@ -157,6 +160,9 @@ class Scheduler:
                         r.status = "done" if ok else "failed"
                         self.used -= r.nbytes
                         done.append(r)
+                    if self.on_complete is not None:
+                        for r in rs:
+                            self.on_complete(r)
                     del inflight[slot]
                     free.append(slot)
                     progressed = True
@@ -230,14 +236,15 @@ def gc_paused():
             gc.collect()
 
 
-def run_plain(executor, requests: List[Request], clock=None) -> List[Request]:
+def run_plain(executor, requests: List[Request], clock=None, on_complete=None) -> List[Request]:
     """Baseline: one stack at a time in arrival order, each waited for
-    before the next starts (no overlap, no batching)."""
+    before the next starts (no overlap, no batching).  ``on_complete`` as
+    for :class:`Scheduler`."""
     with gc_paused():
-        return _run_plain(executor, requests, clock)
+        return _run_plain(executor, requests, clock, on_complete)
 
 
-def _run_plain(executor, requests: List[Request], clock=None) -> List[Request]:
+def _run_plain(executor, requests: List[Request], clock=None, on_complete=None) -> List[Request]:
     clock = clock or RealClock()
     out = []
     for r in sorted(requests, key=lambda q: q.t_arrival):
@@ -253,6 +260,8 @@ def _run_plain(executor, requests: List[Request], clock=None) -> List[Request]:
         r.t_done = clock.now()
         r.status = "done" if ok else "failed"
         out.append(r)
+        if on_complete is not None:
+            on_complete(r)
     return out
 
 
@@ -334,8 +343,10 @@ class GPUExecutor:
     [cols] tensor; a request uses its first ``planes`` planes), standing in
     for camera frames already delivered to HBM.  Each submit is ONE
     persistent launch over all channels of all requests in the batch on the
-    slot's stream, followed by the projections' copy to the slot's pinned
-    staging buffer and an event.
+    slot's stream, followed by the projections' copy to a pinned host
+    buffer of the batch and an event; each request's results are views of
+    that buffer (it is freed, back to the pinned-memory cache, when they
+    are).
 
     Outputs live in one device arena of ``arena_bytes`` reserved up front
     (first fit, freed at completion; :class:`NoSpace` when fragmented), so
@@ -358,7 +369,7 @@ class GPUExecutor:
         self.keep_results = False
         self.arena = Arena(arena_bytes, align=256)
         self.buf = None                            # reserved on first use
-        self.staging = [None] * n_slots           # pinned float32 host buffers
+
 
     def width(self, r):
         from . import api
@@ -394,13 +405,14 @@ class GPUExecutor:
             base = self.arena.alloc(total)        # raises NoSpace when fragmented
         launched = False
         try:
+            # the batch's projections go to one pinned host buffer of its own,
+            # from the framework's caching pinned allocator; the requests'
+            # results are views of it, so it lives while they do and then
+            # returns to the cache (reused only after the copies into it
+            # have completed) -- no copy out and no fresh pageable memory
+            # per request
             proj = sum(2 * rows * w for (_, _, _, rows, w) in items)
-            st = self.staging[slot]
-            if st is None or st.numel() < proj:
-                # pinned allocation is slow: grow at least twofold
-                grow = max(proj, 1 << 20, 2 * (st.numel() if st is not None else 0))
-                st = torch.empty((grow,), dtype=torch.float32, pin_memory=True)
-                self.staging[slot] = st
+            st = torch.empty((max(proj, 1),), dtype=torch.float32, pin_memory=True)
             jobs, outs, host = [], [], []
             off = 0
             hoff = 0
@@ -454,7 +466,7 @@ class GPUExecutor:
         for (r, ch, res), (hp, hm) in zip(outs, host):
             if r.result is None:
                 r.result = {}
-            keep = {"psum": hp.clone(), "pmax": hm.clone()}
+            keep = {"psum": hp, "pmax": hm}
             if self.keep_results and "vol" in res:
                 keep["vol"] = res["vol"]
             r.result[ch] = keep

@@ -171,3 +171,22 @@ def test_scheduler_pauses_and_restores_the_cyclic_collector():
     assert [r.status for r in done] == ["done"] * 4
     assert seen and not any(seen)
     assert gc.isenabled() == was
+
+
+def test_on_complete_sees_every_request_once_after_it_is_done():
+    seen = []
+
+    def hook(r):
+        assert r.status == "done" and r.t_done >= r.t_arrival
+        seen.append(r.rid)
+
+    clk = FakeClock()
+    ex = MockExecutor(clk, s_per_byte=1e-9)
+    Scheduler(ex, budget_bytes=10**12, n_slots=2, clock=clk, on_complete=hook).run(
+        _reqs([0.0, 0.001, 0.002, 0.5]))
+    assert sorted(seen) == [0, 1, 2, 3]
+    seen.clear()
+    clk2 = FakeClock()
+    run_plain(MockExecutor(clk2, s_per_byte=1e-9), _reqs([0.0, 0.1]), clock=clk2,
+              on_complete=hook)
+    assert seen == [0, 1]
