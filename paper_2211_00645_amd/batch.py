@@ -12,6 +12,7 @@ identical to its own single-stack call in either mode.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 
@@ -56,6 +57,26 @@ def plan_job(stack, angle_deg, step_um, pixel_um, vol=True, psum=True, pmax=True
     return job, res
 
 
+@contextlib.contextmanager
+def _tune_cache(path):
+    """Point the library's tune cache (the DSK_TUNE_CACHE variable, read at
+    each lookup) at ``path`` for one call, then restore the previous value:
+    a batch's cache file does not leak into later calls of the process."""
+    if path is None:
+        yield
+        return
+    key = "DSK_TUNE_CACHE"
+    prev = os.environ.get(key)
+    os.environ[key] = str(path)
+    try:
+        yield
+    finally:
+        if prev is None:
+            os.environ.pop(key, None)
+        else:
+            os.environ[key] = prev
+
+
 class Batch:
     """One graph launch over ragged stacks (persistent kernel or one launch
     per job, see :attr:`mode`).
@@ -71,8 +92,6 @@ class Batch:
                  cache_path=None, stream=None):
         if len(stacks) != len(geoms) or not stacks:
             raise ValueError("need one geometry per stack")
-        if cache_path is not None:
-            os.environ["DSK_TUNE_CACHE"] = str(cache_path)
         self.stacks = list(stacks)
         self.outputs = []
         jobs = (L.Job * len(stacks))()
@@ -82,8 +101,9 @@ class Batch:
         self._jobs = jobs
         handle = ctypes.c_void_p()
         tn = api._tune(tune)
-        st = L.lib().dsk_batch_create(jobs, len(stacks), ctypes.byref(tn) if tn else None,
-                                      api._stream(stream), ctypes.byref(handle))
+        with _tune_cache(cache_path):
+            st = L.lib().dsk_batch_create(jobs, len(stacks), ctypes.byref(tn) if tn else None,
+                                          api._stream(stream), ctypes.byref(handle))
         L.check(st, "dsk_batch_create")
         self._h = handle
 

@@ -207,4 +207,12 @@ def test_calibration_recovers_32_degrees(cfg4):
     # calibration is what recovers the angle
     _say(f"calibration: {angle:.6f} deg after {len(hist)} iterations")
     assert abs(angle - 32.0) <= 0.01
-    assert hist[-1][1] < 1e-3 * max(h[1] for h in hist)
+
+    def full_loss(a):
+        """0.5 ||D(a) - D_oracle(32 deg)||^2 over all planes, FP64 sum."""
+        offs = ag.offsets_from_angle(torch.tensor(a, dtype=torch.float64, device=DEV), N4,
+                                     STEP, PIXEL)
+        vol = dsk.deskew(st, offsets=offs, origin=0, width=W4, psum=False, pmax=False)["vol"]
+        return 0.5 * float((vol.double() - target.double()).pow(2).sum())
+
+    assert full_loss(angle) < 1e-3 * full_loss(30.0)

@@ -126,19 +126,28 @@ def test_every_shape_same_bits(small, tune):
     b.close()
 
 
-def test_batch_matches_oracle(small):
+@pytest.mark.parametrize("tune", [dict(block=128, per_thread=4, unroll=2, nt_store=0), None])
+def test_batch_matches_oracle(small, tune):
+    """Every job of the batch -- in a given persistent shape, and in the
+    mode the autotuner picks -- against the oracle at the forward bar: the
+    volume per voxel, padding exactly zero, and both projections within
+    1e-5 relative."""
     stacks, geoms = small
-    b = Batch(stacks, geoms, tune=dict(block=128, per_thread=4, unroll=2, nt_store=0))
+    b = Batch(stacks, geoms, tune=tune)
     b.launch()
     torch.cuda.synchronize()
-    for i in (0, 3, 7):
+    _say(f"batch vs oracle: mode {b.mode}")
+    for i in range(len(stacks)):
         sn = stacks[i].cpu().numpy()
         off = oracle.offsets_uniform(sn.shape[0], oracle.shift_px(*geoms[i]))
         ref = oracle.deskew(sn, off)
-        g = b.outputs[i]["vol"].cpu().numpy().astype(np.float64)
-        r = ref["vol"].astype(np.float64)
-        assert (np.abs(g - r) <= 1e-5 * np.abs(r)).all()
-        assert (g[r == 0] == 0).all()
+        o = b.outputs[i]
+        assert (o["origin"], o["width"]) == (ref["origin"], ref["width"]), i
+        for k in ("vol", "psum", "pmax"):
+            g = o[k].cpu().numpy().astype(np.float64)
+            r = ref[k].astype(np.float64)
+            assert (np.abs(g - r) <= 1e-5 * np.abs(r)).all(), (i, k)
+        assert (o["vol"].cpu().numpy()[ref["vol"] == 0] == 0).all(), i
     b.close()
 
 

@@ -14,15 +14,17 @@ DEV = "cuda:0"
 
 
 def _check_oracle(res, chan_np, angle):
+    """The forward bar: uint16 input has no cancellation, so every voxel and
+    both projections are within 1e-5 of the oracle, relative, with no
+    absolute slack, and padding voxels are exactly zero."""
     o = oracle.deskew(chan_np, oracle.offsets_uniform(chan_np.shape[0],
                                                       oracle.shift_px(angle, 0.4, 0.115)))
-    for k in ("psum", "pmax"):
+    assert (res["origin"], res["width"]) == (o["origin"], o["width"])
+    for k in ("vol", "psum", "pmax"):
         got = res[k].cpu().numpy().astype(np.float64)
         want = o[k].astype(np.float64)
-        assert np.all(np.abs(got - want) <= 2e-5 * np.abs(want) + 1e-6), k
-    got = res["vol"].cpu().numpy().astype(np.float64)
-    want = o["vol"].astype(np.float64)
-    assert np.all(np.abs(got - want) <= 2e-5 * np.abs(want) + 1e-6)
+        assert np.all(np.abs(got - want) <= 1e-5 * np.abs(want)), k
+    assert (res["vol"].cpu().numpy()[o["vol"] == 0] == 0).all()
 
 
 @pytest.mark.parametrize("shape,col0s,cols", [
@@ -41,7 +43,9 @@ def test_channels_equal_dense_copies(shape, col0s, cols):
         torch.cuda.synchronize()
         for k in ("vol", "psum", "pmax"):
             assert torch.equal(res[k], ref[k]), (c0, k)
-    _check_oracle(outs[-1], frames[:, :, col0s[-1]:col0s[-1] + cols].cpu().numpy(), 35.0)
+    host = frames.cpu().numpy()
+    for c0, res in zip(col0s, outs):
+        _check_oracle(res, np.ascontiguousarray(host[:, :, c0:c0 + cols]), 35.0)
 
 
 def test_two_channels_full_size():

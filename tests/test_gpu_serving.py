@@ -1,8 +1,11 @@
 """Serving loop on the GPU: every result is bitwise the same alone and in the
-mix of overlapping, batched requests; the memory budget holds."""
+mix of overlapping, batched requests, and within the forward bar of the
+oracle; the memory budget holds."""
+import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_2211_00645_amd as dsk
 from paper_2211_00645_amd import synth
 from paper_2211_00645_amd.serving import GPUExecutor, Request, Scheduler, run_plain, summarize
@@ -50,6 +53,28 @@ def _check_alone(pool, reqs):
             assert torch.equal(got["vol"], solo["vol"]), (r.rid, ch)
 
 
+def _check_oracle(r, ch, stack_rows, rows, got, vol=None):
+    """A served result against the oracle at the forward bar: projections
+    (and the volume, when kept) within 1e-5 relative per element, padding
+    voxels exactly zero.  ``stack_rows`` is the request's channel stack
+    restricted to ``rows`` (rows are independent in the remap)."""
+    sn = stack_rows.cpu().numpy()
+    offs = oracle.offsets_uniform(sn.shape[0], oracle.shift_px(r.angle_deg, r.step_um,
+                                                                r.pixel_um))
+    ref = oracle.deskew(sn, offs, vol=vol is not None)
+    assert ref["width"] == r.width, (r.rid, ch)
+    r0, r1 = rows
+    for k in ("psum", "pmax"):
+        g = got[k][r0:r1].cpu().numpy().astype(np.float64)
+        o = ref[k].astype(np.float64)
+        assert (np.abs(g - o) <= 1e-5 * np.abs(o)).all(), (r.rid, ch, k)
+    if vol is not None:
+        g = vol[:, r0:r1].cpu().numpy().astype(np.float64)
+        o = ref["vol"].astype(np.float64)
+        assert (np.abs(g - o) <= 1e-5 * np.abs(o)).all(), (r.rid, ch, "vol")
+        assert (g[o == 0] == 0).all(), (r.rid, ch)
+
+
 def test_mixed_requests_equal_solo_runs(pool):
     reqs = _trace(24, 3000.0, 1)          # a burst: requests overlap on the GPU
     ex = GPUExecutor(pool, n_slots=3)
@@ -61,6 +86,11 @@ def test_mixed_requests_equal_solo_runs(pool):
     assert s["done"] == 24
     assert sch.launches < 24              # requests were batched
     _check_alone(pool, done)
+    # and every served result against the oracle (whole stacks)
+    for r in done:
+        for ch in range(2):
+            stack = pool[(r.rows, r.cols, ch)][:r.planes]
+            _check_oracle(r, ch, stack, (0, r.rows), r.result[ch], vol=r.result[ch]["vol"])
 
 
 def test_budget_holds_and_plain_baseline(pool):
@@ -142,5 +172,9 @@ def test_full_size_burst_projections_equal_solo_runs():
             torch.cuda.synchronize()
             assert torch.equal(r.result[ch]["psum"], solo["psum"].cpu()), (r.rid, ch)
             assert torch.equal(r.result[ch]["pmax"], solo["pmax"].cpu()), (r.rid, ch)
+            # sampled rows of the served projections against the oracle
+            for r0 in (0, r.rows // 2 + 1, r.rows - 2):
+                st = big[(r.rows, r.cols, ch)][:r.planes, r0:r0 + 2].contiguous()
+                _check_oracle(r, ch, st, (r0, r0 + 2), r.result[ch])
     del big, ex
     torch.cuda.empty_cache()

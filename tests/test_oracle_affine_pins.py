@@ -29,6 +29,24 @@ def test_frame_is_the_scan_range_of_the_corners():
     assert ny == math.floor((49 * 0.1 * math.cos(math.radians(30)) + 2.7) / 0.05) + 1
 
 
+@pytest.mark.parametrize("n,c,ang,step,pix,dy", [(7, 13, 35.0, 0.4, 0.115, 0.115),
+                                                 (10, 50, 30.0, -0.3, 0.1, 0.05),
+                                                 (5, 9, 60.0, 0.25, 0.2, 0.07),
+                                                 (1, 6, 45.0, 0.4, 0.1, 0.03),
+                                                 (12, 1, 20.0, -0.5, 0.1, 0.2)])
+def test_frame_is_the_smallest_grid_covering_every_pixel(n, c, ang, step, pix, dy):
+    """Brute force over every raw pixel's scan coordinate n z + c p cos(alpha):
+    the grid starts at the smallest, its last slice lies at or before the
+    largest and one more slice would lie beyond it."""
+    pc = pix * math.cos(math.radians(ang))
+    ys = [k * step + j * pc for k in range(n) for j in range(c)]
+    y0, ny = oracle.affine_frame(n, c, ang, step, pix, dy)
+    assert y0 == pytest.approx(min(ys), abs=1e-12)
+    top = max(ys)
+    assert y0 + (ny - 1) * dy <= top + 1e-12
+    assert y0 + ny * dy > top + 1e-12
+
+
 def test_sheet_along_scan_axis_is_an_index_shear():
     """alpha = 0, unit pixel, step and y-step: image coordinate u = y - z
     exactly, so V[y, x, z] = S[y - z, x, z] (zero outside)."""

@@ -51,6 +51,21 @@ def test_warp_reproduces_linear_rows(wf):
     np.testing.assert_allclose(out[1], 100.0 - 0.4 * j / wf, rtol=1e-12, atol=1e-11)
 
 
+@pytest.mark.parametrize("w_in,wf", [(200, 0.9999), (200, 0.8660254037844387), (3504, 0.5),
+                                     (37, 0.31), (1, 0.7), (2, 1.0), (4218, 0.8191520442889918),
+                                     (11, 0.5)])
+def test_view_width_is_the_largest_inside_the_row(w_in, wf):
+    """The view keeps exactly the columns j = 0, 1, ... whose sample point
+    j / wf lies on the projection row (at most the last column's centre
+    w_in - 1): counted one by one, and the next column falls outside."""
+    w = oracle.view_width(w_in, wf)
+    inside = 0
+    while inside / wf <= w_in - 1:
+        inside += 1
+    assert w == inside
+    assert (w - 1) / wf <= w_in - 1 < w / wf
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_warp_equals_dense_hat_matrix(seed):
     rng = np.random.default_rng(seed)
