@@ -340,6 +340,12 @@ int dsk_view_u16(const uint16_t *in, dsk_dims d, double shear_px,
                  float *vsum, float *vmax, int64_t view_width,
                  void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* Columns of a row of width_in stretched by `stretch` (> 0): every output
+ * column up to the last input column's position,
+ * floor((width_in - 1) * stretch) + 1, into *width_out (host).  Host only;
+ * dsk_view_plan's view width is this of the projection width. */
+int dsk_stretch_width(int64_t width_in, double stretch, int64_t *width_out);
+
 /* The stretch alone: out[r][j] = linear interpolation of proj[r][.] at
  * j / stretch (zero outside [0, width_in)); proj [rows][width_in], out
  * [rows][width_out], both DEVICE float32. */

@@ -89,6 +89,7 @@ _SIGS = {
     "dsk_view_workspace_bytes": (c_sz, [Dims, c_i64]),
     "dsk_view_u16": (ctypes.c_int, [c_vp, Dims, c_dbl, c_dbl, c_i64, c_i64, c_vp, c_vp, c_i64,
                                     c_vp, c_sz, c_vp]),
+    "dsk_stretch_width": (ctypes.c_int, [c_i64, c_dbl, ctypes.POINTER(c_i64)]),
     "dsk_stretch_f32": (ctypes.c_int, [c_vp, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp]),
     "dsk_affine_plan": (ctypes.c_int, [Dims, Geom, c_dbl, ctypes.POINTER(c_dbl),
                                        ctypes.POINTER(c_i64)]),

@@ -306,7 +306,10 @@ def stretch(proj, factor, width=None, stream=None):
         raise ValueError("proj must be a contiguous float32 CUDA tensor [rows][W]")
     rows, w_in = proj.shape
     if width is None:
-        width = int(np.floor((w_in - 1) * float(factor))) + 1
+        wout = ctypes.c_int64()
+        L.check(L.lib().dsk_stretch_width(w_in, float(factor), ctypes.byref(wout)),
+                "dsk_stretch_width")
+        width = wout.value
     out = torch.empty((rows, int(width)), dtype=torch.float32, device=proj.device)
     st = L.lib().dsk_stretch_f32(_vp(proj), rows, w_in, float(factor), _vp(out), int(width),
                                  _stream(stream))

@@ -67,6 +67,17 @@ void launch_stretch(const float *proj, int64_t rows, int64_t win, double stretch
 
 }  // namespace
 
+// Columns of a stretched row: the last input column (width_in - 1) lands at
+// (width_in - 1) * stretch, and the output keeps every column up to it.
+extern "C" int dsk_stretch_width(int64_t width_in, double stretch, int64_t *width_out) {
+    if (!width_out || width_in <= 0 || !std::isfinite(stretch) || !(stretch > 0.0))
+        return DSK_EINVAL;
+    const double last = std::floor((double)(width_in - 1) * stretch);
+    if (!(last < 1.0e15)) return DSK_ESHAPE;
+    *width_out = (int64_t)last + 1;
+    return DSK_OK;
+}
+
 extern "C" int dsk_view_plan(dsk_dims d, dsk_geom g, double theta_deg, double *shear_px,
                              double *stretch, int64_t *proj_width, int64_t *origin,
                              int64_t *view_width) {
@@ -82,7 +93,9 @@ extern "C" int dsk_view_plan(dsk_dims d, dsk_geom g, double theta_deg, double *s
     int64_t w = 0, b = 0;
     const int st = dsk_plan(d, nullptr, s, &w, &b);
     if (st != DSK_OK) return st;
-    const int64_t vw = (int64_t)std::floor((double)(w - 1) * c) + 1;
+    int64_t vw = 0;
+    const int sw = dsk_stretch_width(w, c, &vw);
+    if (sw != DSK_OK) return sw;
     if (shear_px) *shear_px = s;
     if (stretch) *stretch = c;
     if (proj_width) *proj_width = w;

@@ -173,6 +173,18 @@ def test_view_entry_points_reject_bad_arguments_before_any_launch():
     assert lib.dsk_stretch_f32(fake, 2, 20, 0.9, None, 18, None) == L.DSK_EINVAL
 
 
+@pytest.mark.parametrize("w_in,factor", [(1, 0.5), (3504, 1.0), (4218, 0.8191520442889918),
+                                          (3778, 0.9659258262890683), (10, 2.5), (7, 1e-9)])
+def test_stretch_width_is_the_oracle_view_width(w_in, factor):
+    import oracle
+    out = ctypes.c_int64()
+    assert L.lib().dsk_stretch_width(w_in, factor, ctypes.byref(out)) == L.DSK_OK
+    assert out.value == oracle.view_width(w_in, factor)
+    for bad in (0.0, -1.0, float("nan")):
+        assert L.lib().dsk_stretch_width(w_in, bad, ctypes.byref(out)) == L.DSK_EINVAL
+    assert L.lib().dsk_stretch_width(0, factor, ctypes.byref(out)) == L.DSK_EINVAL
+
+
 def test_channel_entry_point_rejects_ranges_outside_the_frame():
     lib = L.lib()
     d = L.Dims(4, 2, 8)
