@@ -202,6 +202,28 @@ int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims d,
                      void *workspace, size_t workspace_bytes,
                      hipStream_t stream);
 
+/* dsk_backward_f32 for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no workspace argument; the shear gradient's partial sums go
+ * to a library-owned device array of 1 MiB (131072 doubles), one per
+ * device, held until the process ends.  It needs
+ * dsk_shear_grad_workspace_bytes(d) <= 1048576, i.e.
+ * planes * ceil(rows / clamp(8192 / cols, 1, rows)) <= 131072 (the
+ * 256 x 512 x 1024 stack needs 16384); beyond that it returns DSK_ESHAPE
+ * and enqueues nothing.  The array is looked up once per device (on the
+ * first call with grad_offsets set, with that device current) and never
+ * needs clearing: every partial is written before it is read.  Calls on one
+ * device share its array, so calls that may overlap on one device (two
+ * streams, two threads) race: serialise them, or use dsk_backward_f32 with
+ * a workspace per stream.  Arguments, outputs and errors otherwise as
+ * dsk_backward_f32; results are bitwise identical to it.  Calls no
+ * hipMalloc, hipFree or allocating routine. */
+int dsk_backward_f32_noalloc(const float *in, const float *grad_vol,
+                             dsk_dims d, const double *offsets_dev,
+                             int64_t origin, int64_t out_width,
+                             float *grad_in, double *grad_offsets,
+                             hipStream_t stream);
+
 /* ---------------------------------------------------------------------
  * Ragged batches: many uint16 stacks of different sizes and geometries in
  * one graph launch.  The graph holds either one persistent kernel (one

@@ -69,6 +69,8 @@ _SIGS = {
                                           c_sz, c_vp]),
     "dsk_backward_f32": (ctypes.c_int, [c_vp, c_vp, Dims, c_vp, c_i64, c_i64, c_vp, c_vp, c_vp,
                                         c_sz, c_vp]),
+    "dsk_backward_f32_noalloc": (ctypes.c_int, [c_vp, c_vp, Dims, c_vp, c_i64, c_i64, c_vp,
+                                                c_vp, c_vp]),
     "dsk_batch_create": (ctypes.c_int, [ctypes.POINTER(Job), ctypes.c_int,
                                         ctypes.POINTER(Tune), c_vp, ctypes.POINTER(c_vp)]),
     "dsk_batch_launch": (ctypes.c_int, [c_vp, c_vp]),

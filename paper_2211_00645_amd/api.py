@@ -194,11 +194,14 @@ def deskew(stack: torch.Tensor, angle_deg=None, step_um=None, pixel_um=None, *,
 
 
 def backward(stack, grad_vol, offsets_dev, origin, *, grad_in=True, grad_offsets=True,
-             stream=None):
+             stream=None, noalloc=False):
     """Adjoint (grad wrt the float32 stack) and/or per-plane shear gradient.
 
     ``offsets_dev`` is a float64 CUDA tensor; ``grad_vol`` is float32
     [planes][rows][width].  Returns (grad_in or None, grad_offsets or None).
+    ``noalloc`` calls the library's allocation-free variant (its partial
+    sums in a library-owned device array; calls on one device must not
+    overlap) instead of passing a workspace.
     """
     _check_stack(grad_vol, (torch.float32,))
     _check_stack(stack, (torch.float32,))
@@ -214,6 +217,11 @@ def backward(stack, grad_vol, offsets_dev, origin, *, grad_in=True, grad_offsets
     gi = torch.empty((n, r, c), dtype=torch.float32, device=dev) if grad_in else None
     go = torch.empty((n,), dtype=torch.float64, device=dev) if grad_offsets else None
     lib = L.lib()
+    if noalloc:
+        st = lib.dsk_backward_f32_noalloc(_vp(stack), _vp(grad_vol), dims, _vp(offsets_dev),
+                                          int(origin), int(w), _vp(gi), _vp(go), _stream(stream))
+        L.check(st, "dsk_backward_f32_noalloc")
+        return gi, go
     ws = None
     wsb = 0
     if grad_offsets:

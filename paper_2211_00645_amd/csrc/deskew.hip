@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "common.hpp"
 #include "deskew.h"
@@ -253,6 +254,11 @@ int bwd_groups(dsk_dims d) {
     return (d.rows + rpb - 1) / rpb;
 }
 
+bool gvol_ok(const float *gvol, const double *offs, dsk_dims d, const float *gin,
+             const double *goff) {
+    return gvol && offs && dims_ok(d) && (gin || goff);
+}
+
 int launch_backward(const float *in, const float *gvol, dsk_dims d, const double *offs,
                     int64_t origin, int64_t width, float *gin, double *goff, void *ws,
                     size_t ws_bytes, hipStream_t stream) {
@@ -314,4 +320,59 @@ extern "C" int dsk_backward_f32(const float *in, const float *grad_vol, dsk_dims
                                 size_t workspace_bytes, hipStream_t stream) {
     return launch_backward(in, grad_vol, d, offsets_dev, origin, out_width, grad_in,
                            grad_offsets, workspace, workspace_bytes, stream);
+}
+
+// ------------------------------------------------- backward, no allocation
+//
+// The shear gradient's per-(plane, row-group) partial sums live in a
+// file-scope device array instead of a caller workspace.  Each device holds
+// its own copy of the array; host code reaches it only through the address
+// hipGetSymbolAddress returns for that device (the array's name is a host
+// stand-in, not a device address).  Every partial is written by the
+// backward kernel before the finalize kernel reads it, so nothing needs
+// clearing between calls.
+
+namespace {
+
+constexpr size_t kScratchBytes = size_t(1) << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {nullptr};
+
+// Address of the current device's scratch array, looked up once per device.
+int scratch_for_current_device(void **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return DSK_EHIP;
+    if (dev < 0 || dev >= kMaxDevices) return DSK_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return DSK_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DSK_OK;
+}
+
+}  // namespace
+
+extern "C" int dsk_backward_f32_noalloc(const float *in, const float *grad_vol, dsk_dims d,
+                                        const double *offsets_dev, int64_t origin,
+                                        int64_t out_width, float *grad_in,
+                                        double *grad_offsets, hipStream_t stream) {
+    if (!gvol_ok(grad_vol, offsets_dev, d, grad_in, grad_offsets)) return DSK_EINVAL;
+    void *ws = nullptr;
+    if (grad_offsets) {
+        if (dsk_shear_grad_workspace_bytes(d) > kScratchBytes) return DSK_ESHAPE;
+        const int st = scratch_for_current_device(&ws);
+        if (st != DSK_OK) return st;
+    }
+    return launch_backward(in, grad_vol, d, offsets_dev, origin, out_width, grad_in,
+                           grad_offsets, ws, grad_offsets ? kScratchBytes : 0, stream);
 }

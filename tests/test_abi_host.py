@@ -218,3 +218,26 @@ def test_affine_plan_matches_the_oracle_frame_and_rejects_bad_grids():
                               None) == L.DSK_EINVAL
     assert lib.dsk_affine_u16(fake, d, L.Geom(30.0, 0.4, 0.1), 0.1, float("nan"), 5, fake,
                               None) == L.DSK_EINVAL
+
+
+def test_noalloc_backward_rejects_before_touching_a_device():
+    """The allocation-free backward validates on the host: a shape whose
+    shear-gradient partials exceed its 1 MiB device array is DSK_ESHAPE,
+    missing pointers are DSK_EINVAL, and neither reaches the device (the
+    pointers below are never dereferenced)."""
+    lib = L.lib()
+    fake = 4096
+    big = L.Dims(4097, 4096, 64)          # 4097 planes x 32 row groups of 128 rows
+    assert lib.dsk_shear_grad_workspace_bytes(big) > (1 << 20)
+    assert lib.dsk_backward_f32_noalloc(fake, fake, big, fake, 0, 100, fake, fake,
+                                        None) == L.DSK_ESHAPE
+    ok = L.Dims(256, 512, 1024)            # the autograd stack fits
+    assert lib.dsk_shear_grad_workspace_bytes(ok) <= (1 << 20)
+    assert lib.dsk_backward_f32_noalloc(fake, None, ok, fake, 0, 1793, fake, fake,
+                                        None) == L.DSK_EINVAL
+    assert lib.dsk_backward_f32_noalloc(fake, fake, ok, None, 0, 1793, fake, fake,
+                                        None) == L.DSK_EINVAL
+    assert lib.dsk_backward_f32_noalloc(fake, fake, ok, fake, 0, 1793, None, None,
+                                        None) == L.DSK_EINVAL
+    assert lib.dsk_backward_f32_noalloc(fake, fake, L.Dims(0, 1, 1), fake, 0, 1, fake, fake,
+                                        None) == L.DSK_EINVAL
