@@ -19,6 +19,16 @@
 
 using namespace dsk;
 
+// One persistent launch: `count` job records from `first` in the table, all
+// writing a volume or none (each kind has its own kernel), their tiles
+// numbered from 0.
+struct SubLaunch {
+    int first = 0, count = 0;
+    int64_t total = 0;
+    int grid = 0;
+    bool vol = false;
+};
+
 struct dsk_batch {
     int device = 0;
     int n_jobs = 0;
@@ -27,8 +37,8 @@ struct dsk_batch {
     std::vector<dsk_tune> job_tunes;     // per-job shapes (DSK_BATCH_PER_JOB_TUNED)
     dsk_tune tune{};
     double best_ms = 0.0;
-    int64_t total_tiles = 0;
-    int grid = 0;
+    SubLaunch subs[2];                   // persistent launches (see encode_table)
+    int n_subs = 0;
     JobDev *table_dev = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -38,10 +48,12 @@ namespace {
 
 using JobsKernel = void (*)(const JobDev *, int, int64_t);
 
-JobsKernel pick_kernel(const dsk_tune &t) {
-    return dispatch_tune(t, [](auto B, auto P, auto U, auto NT) -> JobsKernel {
-        return k_forward_jobs<decltype(B)::value, decltype(P)::value, decltype(U)::value,
-                              decltype(NT)::value>;
+JobsKernel pick_kernel(const dsk_tune &t, bool vol) {
+    return dispatch_tune(t, [vol](auto B, auto P, auto U, auto NT) -> JobsKernel {
+        constexpr int b = decltype(B)::value, p = decltype(P)::value, u = decltype(U)::value;
+        // launches without a volume only read: no store kind to choose
+        if (vol) return k_forward_jobs<b, p, u, decltype(NT)::value, true>;
+        return k_forward_jobs<b, p, u, false, false>;
     });
 }
 
@@ -51,47 +63,64 @@ int validate_job(const dsk_job &j) {
     return check_frame(j.dims, j.origin, j.out_width);
 }
 
-// Job table for a launch shape; returns the total tile count (or < 0).
-int64_t encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out) {
-    int64_t begin = 0;
-    for (int i = 0; i < n; ++i) {
-        const dsk_job &j = jobs[i];
-        const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol,
-                                (int64_t)j.dims.rows * j.dims.cols);
-        const int64_t tx = tiles_x(j.out_width, t, vec);
-        const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec);
-        if (tx > kMaxI32) return -1;
-        JobDev r;
-        r.in = j.in;
-        r.vol = j.vol;
-        r.psum = j.psum;
-        r.pmax = j.pmax;
-        r.offs = j.offsets_dev;
-        r.shift = j.shift_px;
-        r.origin = (double)j.origin;
-        r.W = j.out_width;
-        r.tile_begin = begin;
-        r.N = j.dims.planes;
-        r.R = j.dims.rows;
-        r.C = j.dims.cols;
-        r.tiles_x = (int32_t)tx;
-        r.vec = vec ? 1 : 0;
-        r.edge_blocks = (int32_t)eb;
-        r.tau256 = 0;
-        out[i] = r;
-        begin += tx * j.dims.rows + eb;
-        if (begin < 0 || begin > (int64_t(1) << 50)) return -1;
+// Job table for a launch shape: the jobs that write a volume first, then the
+// others, each part numbering its tiles from 0.  Fills one SubLaunch per
+// non-empty part (grid still 0) and returns their number, or < 0.
+int encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out, SubLaunch subs[2]) {
+    int ns = 0, k = 0;
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool vol = pass == 0;
+        const int first = k;
+        int64_t begin = 0;
+        for (int i = 0; i < n; ++i) {
+            const dsk_job &j = jobs[i];
+            if ((j.vol != nullptr) != vol) continue;
+            const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol,
+                                    (int64_t)j.dims.rows * j.dims.cols);
+            const int64_t tx = tiles_x(j.out_width, t, vec);
+            const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec);
+            if (tx > kMaxI32) return -1;
+            JobDev r;
+            r.in = j.in;
+            r.vol = j.vol;
+            r.psum = j.psum;
+            r.pmax = j.pmax;
+            r.offs = j.offsets_dev;
+            r.shift = j.shift_px;
+            r.origin = (double)j.origin;
+            r.W = j.out_width;
+            r.tile_begin = begin;
+            r.N = j.dims.planes;
+            r.R = j.dims.rows;
+            r.C = j.dims.cols;
+            r.tiles_x = (int32_t)tx;
+            r.vec = vec ? 1 : 0;
+            r.edge_blocks = (int32_t)eb;
+            r.tau256 = 0;
+            out[k++] = r;
+            begin += tx * j.dims.rows + eb;
+            if (begin < 0 || begin > (int64_t(1) << 50)) return -1;
+        }
+        if (k > first) {
+            if (begin <= 0) return -1;
+            SubLaunch &sl = subs[ns++];
+            sl.first = first;
+            sl.count = k - first;
+            sl.total = begin;
+            sl.grid = 0;
+            sl.vol = vol;
+        }
     }
-    return begin;
+    return ns;
 }
 
 // Resident workgroups for the persistent grid.
-int persistent_grid(const dsk_tune &t, int64_t total_tiles) {
+int persistent_grid(const dsk_tune &t, bool vol, int64_t total_tiles) {
     int dev = 0, cus = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return -1;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return -1;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick_kernel(t),
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)pick_kernel(t, vol),
                                                      t.block, 0) != hipSuccess)
         return -1;
     if (per_cu < 1) per_cu = 1;
@@ -119,10 +148,29 @@ void set_pacing(JobDev *tab, int n, const dsk_tune &t, int grid) {
     }
 }
 
-hipError_t launch_jobs(const JobDev *table, int n, int64_t total, int grid, const dsk_tune &t,
+// Grids and pacing of the table's persistent launches.
+int plan_launches(const dsk_tune &t, JobDev *table_host, SubLaunch *subs, int ns) {
+    for (int i = 0; i < ns; ++i) {
+        SubLaunch &sl = subs[i];
+        sl.grid = persistent_grid(t, sl.vol, sl.total);
+        if (sl.grid <= 0) return DSK_EHIP;
+        set_pacing(table_host + sl.first, sl.count, t, sl.grid);
+    }
+    return DSK_OK;
+}
+
+hipError_t launch_jobs(const JobDev *table, const SubLaunch *subs, int ns, const dsk_tune &t,
                        hipStream_t s) {
-    void *args[] = {(void *)&table, (void *)&n, (void *)&total};
-    return hipLaunchKernel((const void *)pick_kernel(t), dim3(grid), dim3(t.block), args, 0, s);
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < ns && e == hipSuccess; ++i) {
+        const JobDev *tab = table + subs[i].first;
+        int n = subs[i].count;
+        int64_t total = subs[i].total;
+        void *args[] = {(void *)&tab, (void *)&n, (void *)&total};
+        e = hipLaunchKernel((const void *)pick_kernel(t, subs[i].vol), dim3(subs[i].grid),
+                            dim3(t.block), args, 0, s);
+    }
+    return e;
 }
 
 int log2_bucket(double v) { return v <= 1.0 ? 0 : (int)std::floor(std::log2(v)); }
@@ -152,17 +200,17 @@ std::vector<dsk_tune> candidates() {
 
 int upload_table(dsk_batch *bt, const dsk_tune &t, hipStream_t s) {
     std::vector<JobDev> host((size_t)bt->n_jobs);
-    const int64_t total = encode_table(bt->jobs.data(), bt->n_jobs, t, host.data());
-    if (total <= 0) return DSK_ESHAPE;
-    const int grid = persistent_grid(t, total);
-    if (grid <= 0) return DSK_EHIP;
-    set_pacing(host.data(), bt->n_jobs, t, grid);
+    SubLaunch subs[2];
+    const int ns = encode_table(bt->jobs.data(), bt->n_jobs, t, host.data(), subs);
+    if (ns <= 0) return DSK_ESHAPE;
+    const int st = plan_launches(t, host.data(), subs, ns);
+    if (st != DSK_OK) return st;
     hipError_t e = hipMemcpyAsync(bt->table_dev, host.data(), host.size() * sizeof(JobDev),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return DSK_EHIP;
-    bt->total_tiles = total;
-    bt->grid = grid;
+    for (int i = 0; i < ns; ++i) bt->subs[i] = subs[i];
+    bt->n_subs = ns;
     return DSK_OK;
 }
 
@@ -177,10 +225,10 @@ int time_shape(dsk_batch *bt, const dsk_tune &t, hipStream_t s, int reps, double
         return DSK_EHIP;
     }
     double best = 1e300;
-    hipError_t e = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, t, s);
+    hipError_t e = launch_jobs(bt->table_dev, bt->subs, bt->n_subs, t, s);
     for (int i = 0; i < reps && e == hipSuccess; ++i) {
         e = hipEventRecord(a, s);
-        if (e == hipSuccess) e = launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, t, s);
+        if (e == hipSuccess) e = launch_jobs(bt->table_dev, bt->subs, bt->n_subs, t, s);
         if (e == hipSuccess) e = hipEventRecord(b, s);
         if (e == hipSuccess) e = hipEventSynchronize(b);
         float f = 0.0f;
@@ -200,7 +248,7 @@ int time_shape(dsk_batch *bt, const dsk_tune &t, hipStream_t s, int reps, double
 int launch_per_job(const dsk_batch *bt, bool tuned, hipStream_t s) {
     for (size_t i = 0; i < bt->jobs.size(); ++i) {
         const dsk_job &j = bt->jobs[i];
-        const dsk_tune &t = tuned ? bt->job_tunes[i] : kDefaultTune;
+        const dsk_tune &t = tuned ? bt->job_tunes[i] : default_tune(j.vol);
         const int st = launch_forward(j.in, 0, j.dims, j.offsets_dev, j.shift_px, j.origin, j.vol,
                                       j.psum, j.pmax, j.out_width, t, s);
         if (st != DSK_OK) return st;
@@ -225,8 +273,7 @@ int tune_jobs(dsk_batch *bt, hipStream_t s) {
 int launch_mode(dsk_batch *bt, hipStream_t s) {
     if (bt->mode == DSK_BATCH_PER_JOB) return launch_per_job(bt, false, s);
     if (bt->mode == DSK_BATCH_PER_JOB_TUNED) return launch_per_job(bt, true, s);
-    return hip_status(
-        launch_jobs(bt->table_dev, bt->n_jobs, bt->total_tiles, bt->grid, bt->tune, s));
+    return hip_status(launch_jobs(bt->table_dev, bt->subs, bt->n_subs, bt->tune, s));
 }
 
 // Best of `reps` timed runs (ms) of a per-job mode, after one untimed run.
@@ -383,7 +430,9 @@ extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host
                                hipStream_t stream) {
     if (!jobs || n_jobs <= 0 || !table_host || !table_dev) return DSK_EINVAL;
     if (table_bytes < dsk_jobs_table_bytes(n_jobs)) return DSK_ESHAPE;
-    dsk_tune t = tune ? *tune : kDefaultTune;
+    bool any_vol = false;
+    for (int i = 0; i < n_jobs; ++i) any_vol = any_vol || jobs[i].vol != nullptr;
+    dsk_tune t = tune ? *tune : (any_vol ? kDefaultTune : kDefaultProjTune);
     if (!tune_ok(t)) return DSK_EINVAL;
     for (int i = 0; i < n_jobs; ++i) {
         const int st = validate_job(jobs[i]);
@@ -401,13 +450,13 @@ extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host
         }
     }
     JobDev *host = (JobDev *)table_host;
-    const int64_t total = encode_table(jobs, n_jobs, t, host);
-    if (total <= 0) return DSK_ESHAPE;
-    const int grid = persistent_grid(t, total);
-    if (grid <= 0) return DSK_EHIP;
-    set_pacing(host, n_jobs, t, grid);
+    SubLaunch subs[2];
+    const int ns = encode_table(jobs, n_jobs, t, host, subs);
+    if (ns <= 0) return DSK_ESHAPE;
+    const int st = plan_launches(t, host, subs, ns);
+    if (st != DSK_OK) return st;
     hipError_t e = hipMemcpyAsync(table_dev, host, dsk_jobs_table_bytes(n_jobs),
                                   hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = launch_jobs((const JobDev *)table_dev, n_jobs, total, grid, t, stream);
+    if (e == hipSuccess) e = launch_jobs((const JobDev *)table_dev, subs, ns, t, stream);
     return hip_status(e);
 }

@@ -14,14 +14,25 @@ constexpr int64_t kMaxI32 = 2147483647;
 
 // Default forward launch shape: 64-thread workgroups, one 4-column group per
 // lane, non-temporal stores, 2-plane pipeline (built for 8 waves per SIMD),
-// paced at 5700 GB/s.  On the 512x512x2048 stack, back to back, the pace
-// holds up to about 5850 GB/s (5800: 0.851 ms); faster than that the
-// wavefronts fall behind the schedule, stop sleeping and drift apart
-// (0.83-0.95 ms, erratic), and boxes differ by a few percent, so the
-// default keeps a margin (5700: 0.862 ms, every launch within 1%).  Other
-// frames put the cliff elsewhere (5400-5800 GB/s); dsk_deskew_autotune
-// finds it for a given frame on the device at hand.
-constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
+// paced at 5800 GB/s.  On the 512x512x2048 stack, back to back, the launch
+// time follows the pace (bytes / pace + about 30 us) up to the cliff:
+// 5700: 0.865 ms, 5800: 0.851, 5900: 0.839; past it the wavefronts fall
+// behind the schedule, stop sleeping and drift apart (6000: 0.896, 6100:
+// 0.969, unpaced 1.057).  The cliff sat between 5850 and 6000 GB/s on the
+// devices measured, so the default stays 100-200 GB/s below it; other
+// frames put it elsewhere (5400-6000 GB/s), and dsk_deskew_autotune finds
+// it for a given frame on the device at hand.
+constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5800};
+
+// Default shape of launches without a volume (projections only, the live
+// view): they only read and are not paced; a 4-plane load-ahead keeps
+// enough reads in flight (on the 512x512x2048 stack 0.233 ms against 0.25
+// for 2 planes).
+constexpr dsk_tune kDefaultProjTune = {64, 4, 1, 4, 0, 0};
+
+inline const dsk_tune &default_tune(const void *vol) {
+    return vol ? kDefaultTune : kDefaultProjTune;
+}
 
 inline bool dims_ok(dsk_dims d) {
     return d.planes > 0 && d.rows > 0 && d.cols > 0;

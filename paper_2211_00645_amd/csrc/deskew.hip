@@ -84,7 +84,7 @@ static int vec_resident_per_cu() {
     static int occ = 0;
     if (occ <= 0) {
         int o = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_forward_vec<TIn, B, G, U, NT>, B,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_forward_vec<TIn, B, G, U, NT, true>, B,
                                                          0) != hipSuccess ||
             o <= 0)
             o = 1;
@@ -99,7 +99,9 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
     const dim3 block(B);
     if constexpr (PT >= 4) {
         if (vec) {
-            auto kern = k_forward_vec<TIn, B, PT / 4, U, NT>;
+            // launches without a volume only read: no store kind to choose
+            auto kern = a.vol ? k_forward_vec<TIn, B, PT / 4, U, NT, true>
+                              : k_forward_vec<TIn, B, PT / 4, U, false, false>;
             const int64_t blocks = tiles * a.R + edge;
             if (pace_gbs > 0 && a.vol) {
                 // pacing keeps the volume's write stream local; a launch
@@ -186,7 +188,7 @@ extern "C" int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float 
     st = dsk_plan(d, nullptr, s, &w, &b);
     if (st != DSK_OK) return st;
     if (out_width > 0) w = out_width;
-    return launch_forward(in, 0, d, nullptr, s, b, vol, psum, pmax, w, kDefaultTune, stream);
+    return launch_forward(in, 0, d, nullptr, s, b, vol, psum, pmax, w, default_tune(vol), stream);
 }
 
 extern "C" int dsk_deskew_channel_u16(const uint16_t *frames, int64_t frame_cols, int64_t col0,
@@ -205,7 +207,7 @@ extern "C" int dsk_deskew_channel_u16(const uint16_t *frames, int64_t frame_cols
     const int64_t plane = (int64_t)d.rows * frame_cols;
     const InLayout lay{frame_cols, plane, col0, (int64_t)d.planes * plane - col0};
     return launch_forward_layout(frames + col0, 0, d, lay, nullptr, s, b, vol, psum, pmax, w,
-                                 kDefaultTune, stream);
+                                 default_tune(vol), stream);
 }
 
 extern "C" int dsk_deskew_offsets_u16(const uint16_t *in, dsk_dims d, const double *offsets_dev,
@@ -213,7 +215,7 @@ extern "C" int dsk_deskew_offsets_u16(const uint16_t *in, dsk_dims d, const doub
                                       int64_t out_width, hipStream_t stream) {
     if (!offsets_dev || out_width <= 0) return DSK_EINVAL;
     return launch_forward(in, 0, d, offsets_dev, 0.0, origin, vol, psum, pmax, out_width,
-                          kDefaultTune, stream);
+                          default_tune(vol), stream);
 }
 
 extern "C" int dsk_deskew_offsets_f32(const float *in, dsk_dims d, const double *offsets_dev,
@@ -221,7 +223,7 @@ extern "C" int dsk_deskew_offsets_f32(const float *in, dsk_dims d, const double 
                                       int64_t out_width, hipStream_t stream) {
     if (!offsets_dev || out_width <= 0) return DSK_EINVAL;
     return launch_forward(in, 1, d, offsets_dev, 0.0, origin, vol, psum, pmax, out_width,
-                          kDefaultTune, stream);
+                          default_tune(vol), stream);
 }
 
 extern "C" int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
@@ -230,7 +232,7 @@ extern "C" int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims 
                                         int64_t out_width, const dsk_tune *tune,
                                         hipStream_t stream) {
     if (out_width <= 0) return DSK_EINVAL;
-    const dsk_tune t = tune ? *tune : kDefaultTune;
+    const dsk_tune t = tune ? *tune : default_tune(vol);
     return launch_forward(in, in_is_f32 ? 1 : 0, d, offsets_dev, shift_px, origin, vol, psum,
                           pmax, out_width, t, stream);
 }

@@ -216,15 +216,15 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
 }
 
 // ---- vector variant ------------------------------------------------------
-// Preconditions (checked on the host): rows*W and rows*C are multiples of 4,
-// the stack is 8-byte (uint16) / 16-byte (float) aligned, the volume 16-byte
-// aligned.  Then the flat volume index of (n, r, x') is 4-aligned exactly
-// when x' + r*W is, independently of n, so a thread can own the same group
-// of 4 columns in every plane and still write it with one 16-byte store.
-// The first tile of a row starts up to 3 columns left of 0 to reach that
-// alignment.  Its 5 source pixels come from two aligned 8-byte (16-byte for
-// float) loads and a funnel shift whose amount is the same for the whole
-// tile.
+// Preconditions (checked on the host): rows*W and the plane pitch are
+// multiples of 4, the stack is 8-byte (uint16) / 16-byte (float) aligned,
+// the volume 16-byte aligned.  Then the flat volume index of (n, r, x') is
+// 4-aligned exactly when x' + r*W is, independently of n, so a thread can
+// own the same group of 4 columns in every plane and still write it with one
+// 16-byte store.  The first tile of a row starts up to 3 columns left of 0 to
+// reach that alignment.  A group's 5 source pixels come from one load: 12
+// bytes from a dword-aligned uint16 element (then a 0- or 16-bit funnel shift
+// that is the same for the whole wavefront), or 16 + 4 bytes of float.
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -236,33 +236,34 @@ __device__ __forceinline__ void store_f32x4(float *p, f32x4 v) {
         *(f32x4 *)p = v;
 }
 
-// Raw source window of one 4-column group: the 8 uint16 (16 bytes) starting
-// at the 4-aligned element `off` before the first needed pixel, or the 5
-// floats starting at that pixel (`off + sh`).
+// Raw source window of one 4-column group.  uint16: the 6 pixels (12 bytes)
+// starting at the even element at or one before the first needed pixel;
+// float: the 5 pixels starting at the first needed pixel.  `sh` is the first
+// needed pixel's place in the window (0 or 1 for uint16, 0 for float), the
+// same for every lane of a wavefront in one plane.
 template <typename TIn>
 struct RawWin;
 
 template <>
 struct RawWin<uint16_t> {
-    uint4 q;
-    __device__ __forceinline__ void load(const uint16_t *row, int off, int) {
-        __builtin_memcpy(&q, row + off, sizeof(q));   // 8-byte aligned
+    static constexpr int kAlign = 2;   // window starts are even elements
+    static constexpr int kLen = 6;     // elements read
+    uint32_t e0, e1, e2;
+    __device__ __forceinline__ void load(const uint16_t *p) {
+        const uint32_t *q = (const uint32_t *)__builtin_assume_aligned(p, 4);
+        e0 = q[0];
+        e1 = q[1];
+        e2 = q[2];
     }
     // Wait for the load here (an empty asm that reads the registers), so no
     // load is pending across a loop back-edge: the wait counter is in-order
     // and shared with stores, and a pending load there would make the
     // compiler wait for every store issued since.
     __device__ __forceinline__ void settle() const {
-        asm volatile("" ::"v"(q.x), "v"(q.y), "v"(q.z), "v"(q.w));
+        asm volatile("" ::"v"(e0), "v"(e1), "v"(e2));
     }
-    // The five pixels starting at element sh (0..3) of the window, without
-    // branches: pick the dword pair, then a 0/16-bit funnel shift.
     __device__ __forceinline__ void extract(int sh, float v[5]) const {
-        const bool hi = sh >= 2;
-        const uint32_t e0 = hi ? q.y : q.x;
-        const uint32_t e1 = hi ? q.z : q.y;
-        const uint32_t e2 = hi ? q.w : q.z;
-        const uint32_t b = (uint32_t)(sh & 1) * 16u;
+        const uint32_t b = (uint32_t)sh * 16u;
         const uint32_t a0 = __builtin_amdgcn_alignbit(e1, e0, b);
         const uint32_t a1 = __builtin_amdgcn_alignbit(e2, e1, b);
         const uint32_t a2 = e2 >> b;
@@ -276,11 +277,13 @@ struct RawWin<uint16_t> {
 
 template <>
 struct RawWin<float> {
+    static constexpr int kAlign = 1;
+    static constexpr int kLen = 5;
     float4 a;
     float b;
-    __device__ __forceinline__ void load(const float *row, int off, int sh) {
-        __builtin_memcpy(&a, row + off + sh, sizeof(a));   // 4-byte aligned
-        b = row[off + sh + 4];
+    __device__ __forceinline__ void load(const float *p) {
+        __builtin_memcpy(&a, p, sizeof(a));   // 4-byte aligned
+        b = p[4];
     }
     __device__ __forceinline__ void settle() const {
         asm volatile("" ::"v"(a.x), "v"(a.y), "v"(a.z), "v"(a.w), "v"(b));
@@ -323,21 +326,40 @@ __device__ __forceinline__ int edge_col(const RowGeo &g, int W, int j) {
 // row's last group, so every lane writes whole 16-byte groups (lanes past
 // the end repeat the last group: identical values to identical addresses).
 //
-// Planes are handled in chunks of 64.  For a chunk, lane l of every
+// Per-plane values come 64 planes at a time (a chunk): lane l of every
 // wavefront computes plane (c0 + l)'s coefficients and window offset, and
-// the wavefront classifies each of its groups: all planes read inside the
-// raw row (IN), all outside it (OUT: padding), or otherwise (MIXED).  IN and
-// MIXED chunks run a software-pipelined loop (MIXED with clamped loads and
-// masks); OUT chunks only store zeros.  The per-plane values come from the
-// chunk lanes by readlane, so the scalar unit -- shared by all wavefronts of
-// a compute unit -- does a handful of instructions per plane.
-template <typename TIn, int BLOCK, int G, int UNR, bool NT>
+// the wavefront classifies each plane for each of its groups: every pixel it
+// reads inside the raw row (IN), every pixel outside (OUT: padding), or
+// otherwise (MIXED).  Plane values reach the loop by readlane, so the scalar
+// unit -- shared by all wavefronts of a compute unit -- does a handful of
+// instructions per plane.
+//
+// With a volume (VOL) the tile walks chunk by chunk: an all-OUT chunk only
+// stores zeros, an all-IN chunk runs a software-pipelined loop with plain
+// loads, any other chunk the same loop with clamped loads and masks.  That
+// pass is bound by its stores, and its loop is built to keep them in flight.
+//
+// Without a volume the pass only reads, and a pipeline that drains at every
+// chunk or class boundary leaves the memory system idle each time all
+// wavefronts drain together.  So the tile first finds, per group, the range
+// of planes that touch its columns, then runs one software-pipelined loop
+// over that range: loads go out U planes ahead across chunk boundaries (the
+// next chunk's values computed in advance), always with clamped addresses,
+// and a group of U planes is masked unless all of them are IN.  Planes at
+// the unaligned ends of the range, and planes whose rows lie at a stack end,
+// go one at a time through the exact-bounds path.
+//
+// Every path does the same per-voxel arithmetic and adds planes to the FP64
+// sum in plane order, so no class or pass split changes a bit of the result.
+template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
 struct VecTile {
     enum { OUT = 0, IN = 1, MIXED = 2 };
+    using Win = RawWin<TIn>;
     const FwdArgs<TIn> &a;
-    int r, W, C, N, ca, ng, wv, lane, gmod;
-    // source window offsets (from the row start, in elements) that keep a
-    // 4-aligned 8-element window inside the stack, away from its two ends
+    int r, W, C, N, ca, ng, wv, lane, gpar;
+    // window starts (elements from the row start) that keep a window of
+    // Win::kLen elements, with the load's alignment, inside the stack away
+    // from its two ends
     int lo_off, hi_off;
     int first_special, last_special;   // planes whose row lies at a stack end
     int64_t rstep, ostep;
@@ -350,8 +372,9 @@ struct VecTile {
     uint32_t taug;                     // the same per plane and group
     double acc[G][4];
     float mx[G][4];
-    // chunk lane data (plane c0 + lane)
-    int ls0, lobsh;                    // window start s0, and (s0 - sh) * 4 + sh
+    // chunk lane data (plane c0 + lane): first needed pixel of group 0 (s0),
+    // window start and shift packed as (s0 - sh) * 2 + sh, and the weights
+    int ls0, lwin;
     float lwlo, lwhi;
 
     __device__ __forceinline__ VecTile(const FwdArgs<TIn> &args, int row, int tile)
@@ -367,18 +390,19 @@ struct VecTile {
         alive = base + 64 * wv < ng;
         // the plane pitch is a multiple of 4, so every plane's row start has
         // this residue
-        gmod = (int)(((int64_t)r * a.in_row) & 3);
-        lo_off = -8 + ((-gmod) & 3);
-        hi_off = C - 1 - ((C - 1 + gmod) & 3);
+        constexpr int K = Win::kAlign;
+        gpar = (int)(((int64_t)r * a.in_row) & (K - 1));
+        lo_off = -8 + ((K - (gpar + 8) % K) % K);
+        hi_off = C - 1 - ((C - 1 + gpar) & (K - 1));
         // plane pitch >= 8: only plane 0 can start closer than 8 elements to
         // the readable start and only plane N-1 can end closer than 8 to its end
         const int64_t g0 = (int64_t)r * a.in_row;
         first_special = (g0 - 8 < -a.in_lo) ? 0 : -1;
         last_special = ((int64_t)(N - 1) * rstep + g0 + C + 8 > a.in_hi) ? N - 1 : -1;
         rp0 = a.in + (int64_t)r * a.in_row;
-        op0 = a.vol ? a.vol + (int64_t)r * W : nullptr;
-        tau = a.tau256;
-        if (a.pace_cap > 0) {
+        op0 = VOL ? a.vol + (int64_t)r * W : nullptr;
+        tau = VOL ? a.tau256 : 0;
+        if (VOL && a.pace_cap > 0) {
             const int64_t cap = a.pace_cap, batch = (int64_t)blockIdx.x / cap;
             const int64_t left = (int64_t)gridDim.x - batch * cap;
             const uint64_t t = ((uint64_t)a.tau_wg * (uint64_t)(left < cap ? left : cap)) >> 8;
@@ -430,13 +454,14 @@ struct VecTile {
             o = __dmul_rn((double)n, a.shift);
         }
         const PlaneCoef pc = coef_from_offset(o, a.origin);
-        // window start of group 0; beyond +-2^28 every position lies outside
-        // the row (rows and widths of this kernel are below 2^27): clamp there
+        // first needed pixel of group 0; beyond +-2^28 every position lies
+        // outside the row (rows and widths of this kernel are below 2^27):
+        // clamp there
         const int s0l = ca - pc.k - 1;
         const int s0 = s0l < -(1 << 28) ? -(1 << 28) : (s0l > (1 << 28) ? (1 << 28) : s0l);
-        const int sh = (gmod + s0) & 3;
+        const int sh = (gpar + s0) & (Win::kAlign - 1);
         ls0 = s0;
-        lobsh = (s0 - sh) * 4 + sh;
+        lwin = (s0 - sh) * 2 + sh;
         lwlo = pc.wlo;
         lwhi = pc.whi;
     }
@@ -451,38 +476,79 @@ struct VecTile {
         }
     }
 
-    // Loads of chunk planes [li0, li0 + U) for group g (indices past the
-    // chunk end repeat its last plane: in bounds, never used).  MASK clamps
-    // the window into the row's neighbourhood (lanes reaching outside the
-    // row only read values that are masked afterwards).
-    template <int U, bool MASK>
-    __device__ __forceinline__ void issue(int g, int li0, int cn, const TIn *rpc,
-                                          RawWin<TIn> raw[U]) const {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int li = min(li0 + u, cn - 1);
-            const int v = __builtin_amdgcn_readlane(lobsh, li);
-            int off = (v >> 2) + 4 * gi[g];
-            if (MASK) off = off < lo_off ? lo_off : (off > hi_off ? hi_off : off);
-            raw[u].load(rpc + (int64_t)li * rstep, off, v & 3);
-        }
+    // Window of one plane: the packed start/shift v, clamped into [lo, hi]
+    // when MASK (lanes reaching outside the row only read values that are
+    // masked afterwards).
+    template <bool MASK>
+    __device__ __forceinline__ void fetch(int g, const TIn *rp, int v, Win &w) const {
+        int off = (v >> 1) + 4 * gi[g];
+        if (MASK) off = off < lo_off ? lo_off : (off > hi_off ? hi_off : off);
+        w.load(rp + off);
     }
 
+    // Interpolate one plane from its window (v its packed start/shift).
     template <bool MASK>
-    __device__ __forceinline__ void compute(int g, const RawWin<TIn> &raw, int li, float d[4]) {
-        const int v = __builtin_amdgcn_readlane(lobsh, li);
-        const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
-        const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
-        const int sh = v & 3;
+    __device__ __forceinline__ void compute(int g, const Win &w, int v, float wlo, float whi,
+                                            float d[4]) {
+        const int sh = v & 1;
         float vv[5];
-        raw.extract(sh, vv);
+        w.extract(sh, vv);
         if (MASK) {
-            const int p = (v >> 2) + sh + 4 * gi[g];
+            const int p = (v >> 1) + sh + 4 * gi[g];
 #pragma unroll
             for (int i = 0; i < 5; ++i)
                 if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
         }
         interp(g, vv, wlo, whi, d);
+    }
+
+    __device__ __forceinline__ float lane_f(float x, int li) const {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), li));
+    }
+
+    // One plane with the window clamped to the stack's exact readable
+    // extent when its row lies at a stack end (else to the row's
+    // neighbourhood); lanes whose window moved reload per pixel.  win, wlo,
+    // whi: the plane's chunk lane values, li its lane.
+    __device__ __forceinline__ void single(int g, int n, int li, int win, float wlo_l, float whi_l,
+                                           float d[4]) {
+        constexpr int K = Win::kAlign;
+        const TIn *rp = rp0 + (int64_t)n * rstep;
+        const int v = __builtin_amdgcn_readlane(win, li);
+        const int sh = v & 1;
+        const float wlo = lane_f(wlo_l, li), whi = lane_f(whi_l, li);
+        const int off = (v >> 1) + 4 * gi[g];
+        const int p = off + sh;
+        int lo = lo_off, hi = hi_off;
+        if (n == first_special || n == last_special) {
+            // the readable extent [in - in_lo, in + in_hi), as window starts
+            // of this row with the load's alignment
+            const int64_t grow = rp - a.in;
+            int64_t lo_ok = -grow - a.in_lo, hi_ok = a.in_hi - Win::kLen - grow;
+            lo_ok += (K - ((grow + lo_ok) % K + K) % K) % K;
+            hi_ok -= ((grow + hi_ok) % K + K) % K;
+            lo = (int)(lo_ok > (int64_t)lo ? lo_ok : (int64_t)lo);
+            hi = (int)(hi_ok < (int64_t)hi ? hi_ok : (int64_t)hi);
+        }
+        const int oc = off < lo ? lo : (off > hi ? hi : off);
+        Win raw;
+        raw.load(rp + oc);
+        float vv[5];
+        raw.extract(sh, vv);
+#pragma unroll
+        for (int i = 0; i < 5; ++i)
+            if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
+        if (oc != off) {
+#pragma unroll
+            for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
+        }
+        interp(g, vv, wlo, whi, d);
+    }
+
+    // ---- with a volume ---------------------------------------------------
+
+    __device__ __forceinline__ void store(int g, float *orow, const float d[4]) const {
+        store_f32x4<NT>(orow + xcol(g), f32x4{d[0], d[1], d[2], d[3]});
     }
 
     // Chunk planes [0, cn) for group g, software-pipelined: the loads of the
@@ -491,122 +557,247 @@ struct VecTile {
     // exactly one 16-byte store per lane with no branch around it, so the
     // compiler counts the stores and the wait for the loads leaves them in
     // flight: stores never hold up the plane loop.
-    template <int U, bool MASK, bool VOL>
+    template <int U, bool MASK>
     __device__ __forceinline__ void pipe_loop(int g, int c0, int cn, const TIn *rpc, float *op) {
         const int groups = cn / U;
-        float *o = VOL ? op + xcol(g) : nullptr;
+        float *orow = op;
+        int li = 0;
         if (groups > 0) {
-            RawWin<TIn> cur[U];
-            issue<U, MASK>(g, 0, cn, rpc, cur);
+            Win cur[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                fetch<MASK>(g, rpc + (int64_t)u * rstep, __builtin_amdgcn_readlane(lwin, u), cur[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u].settle();
             for (int k = 0; k < groups; ++k) {
-                RawWin<TIn> nxt[U];
-                issue<U, MASK>(g, (k + 1) * U, cn, rpc, nxt);
+                // the next U planes (past the chunk's end: its last plane,
+                // in bounds, never used)
+                Win nxt[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int ln = min(li + U + u, cn - 1);
+                    fetch<MASK>(g, rpc + (int64_t)ln * rstep, __builtin_amdgcn_readlane(lwin, ln),
+                                nxt[u]);
+                }
                 // a paced wavefront sleeps with the next loads in flight
-                pace_until(t0, taug, pace_pos(g, c0, cn, k * U));
+                pace_until(t0, taug, pace_pos(g, c0, cn, li));
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     float d[4];
-                    compute<MASK>(g, cur[u], k * U + u, d);
-                    if constexpr (VOL) {
-                        store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
-                        o += ostep;
-                    }
+                    compute<MASK>(g, cur[u], __builtin_amdgcn_readlane(lwin, li + u),
+                                  lane_f(lwlo, li + u), lane_f(lwhi, li + u), d);
+                    store(g, orow, d);
+                    orow += ostep;
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     nxt[u].settle();
                     cur[u] = nxt[u];
                 }
+                li += U;
             }
         }
-        for (int li = groups * U; li < cn; ++li) {
-            RawWin<TIn> one[1];
-            issue<1, MASK>(g, li, cn, rpc, one);
+        for (; li < cn; ++li) {
+            Win one;
+            fetch<MASK>(g, rpc + (int64_t)li * rstep, __builtin_amdgcn_readlane(lwin, li), one);
             float d[4];
-            compute<MASK>(g, one[0], li, d);
-            if constexpr (VOL) {
-                store_f32x4<NT>(o, f32x4{d[0], d[1], d[2], d[3]});
-                o += ostep;
+            compute<MASK>(g, one, __builtin_amdgcn_readlane(lwin, li), lane_f(lwlo, li),
+                          lane_f(lwhi, li), d);
+            store(g, orow, d);
+            orow += ostep;
+        }
+    }
+
+    __device__ __forceinline__ void run_volume() {
+        for (int c0 = 0; c0 < N; c0 += 64) {
+            const int cn = min(64, N - c0);
+            chunk(c0);
+            const bool special = (first_special >= c0 && first_special < c0 + cn) ||
+                                 (last_special >= c0 && last_special < c0 + cn);
+            const TIn *rp = rp0 + (int64_t)c0 * rstep;
+            float *op = op0 + (int64_t)c0 * ostep;
+            const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < cn);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                if (special) {
+                    for (int li = 0; li < cn; ++li) {
+                        float d[4];
+                        single(g, c0 + li, li, lwin, lwlo, lwhi, d);
+                        store(g, op + (int64_t)li * ostep, d);
+                    }
+                    continue;
+                }
+                const int cl = cls_of(ls0, g);
+                const uint64_t bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
+                const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
+                if (bout == valid) {
+                    // padding: zero output, nothing added to the sum
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
+                    float *orow = op;
+                    const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+                    for (int li = 0; li < cn; ++li) {
+                        if ((li & 3) == 0) pace_until(t0, taug, pace_pos(g, c0, cn, li));
+                        store(g, orow, z);
+                        orow += ostep;
+                    }
+                } else if (bin == valid) {
+                    pipe_loop<UNR, false>(g, c0, cn, rp, op);
+                } else {
+                    pipe_loop<UNR, true>(g, c0, cn, rp, op);
+                }
             }
         }
     }
 
-    // Chunk planes whose rows lie at a stack end: windows clamped to the
-    // exact stack bounds; lanes whose window moved reload per pixel.
-    __device__ __forceinline__ void slow_loop(int g, int c0, int cn, const TIn *rpc, float *op) {
-        for (int li = 0; li < cn; ++li) {
-            const int n = c0 + li;
-            const TIn *rp = rpc + (int64_t)li * rstep;
-            const int v = __builtin_amdgcn_readlane(lobsh, li);
-            const int sh = v & 3;
-            const float wlo = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwlo), li));
-            const float whi = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(lwhi), li));
-            const int p = (v >> 2) + sh + 4 * gi[g];
-            int lo = lo_off, hi = hi_off;
-            if (n == first_special || n == last_special) {
-                const int64_t grow = rp - a.in;
-                const int64_t lo_ok = -grow - a.in_lo, hi_ok = a.in_hi - 8 - grow;
-                lo = (int)(lo_ok > (int64_t)lo ? lo_ok : (int64_t)lo);
-                hi = (int)(hi_ok < (int64_t)hi ? hi_ok : (int64_t)hi);
-            }
-            const int off = p - sh;
-            const int oc = off < lo ? lo : (off > hi ? hi : off);
-            RawWin<TIn> raw;
-            raw.load(rp, oc, sh);
-            float vv[5], d[4];
-            raw.extract(sh, vv);
+    // ---- projections only ------------------------------------------------
+
+    // Lane values of the chunk at c0 and the wavefront's IN / OUT ballots for
+    // group g (bits of planes past the stack end clear).
+    struct Chunk {
+        int c0, win;
+        float wlo, whi;
+        uint64_t bin, bout;
+    };
+
+    __device__ __forceinline__ void load_chunk(int g, int c0, Chunk &k) {
+        chunk(c0);
+        const int cn = min(64, N - c0);
+        const int cl = cls_of(ls0, g);
+        k.c0 = c0;
+        k.win = lwin;
+        k.wlo = lwlo;
+        k.whi = lwhi;
+        k.bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
+        k.bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
+    }
+
+    // Planes [n0, n1) of group g one at a time (ascending), each with its
+    // chunk's values (k holds the chunk last loaded).
+    __device__ __forceinline__ void singles(int g, int n0, int n1, Chunk &k) {
+        for (int n = n0; n < n1; ++n) {
+            if (n < k.c0 || n >= k.c0 + 64) load_chunk(g, n & ~63, k);
+            float d[4];
+            single(g, n, n - k.c0, k.win, k.wlo, k.whi, d);
+        }
+    }
+
+    // Issue the window loads of planes n .. n + U - 1 (or U times plane n
+    // with rep set), each taking its values from the chunk it lies in: cur
+    // or the next one.
+    template <int U>
+    __device__ __forceinline__ void issue_group(int g, int n, bool rep, const Chunk &cur,
+                                                const Chunk &nxt, Win w[U], int v[U]) const {
 #pragma unroll
-            for (int i = 0; i < 5; ++i)
-                if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
-            if (oc != off) {
+        for (int u = 0; u < U; ++u) {
+            const int p = rep ? n : n + u;
+            const bool in_nxt = p >= cur.c0 + 64;
+            const int vv = __builtin_amdgcn_readlane(in_nxt ? nxt.win : cur.win,
+                                                     p - (in_nxt ? nxt.c0 : cur.c0));
+            v[u] = vv;
+            fetch<true>(g, rp0 + (int64_t)p * rstep, vv, w[u]);
+        }
+    }
+
+    // Interpolate and accumulate planes n .. n + U - 1 (all in chunk cur),
+    // masked unless all of them are IN.
+    template <int U>
+    __device__ __forceinline__ void compute_group(int g, int n, const Chunk &cur, const Win w[U],
+                                                  const int v[U]) {
+        const int li = n - cur.c0;
+        const uint64_t full = (U == 64) ? ~0ull : ((1ull << U) - 1);
+        float d[4];
+        if (((cur.bin >> li) & full) == full) {
 #pragma unroll
-                for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
+            for (int u = 0; u < U; ++u)
+                compute<false>(g, w[u], v[u], lane_f(cur.wlo, li + u), lane_f(cur.whi, li + u), d);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                compute<true>(g, w[u], v[u], lane_f(cur.wlo, li + u), lane_f(cur.whi, li + u), d);
+        }
+    }
+
+    __device__ __forceinline__ void run_projections() {
+        constexpr int U = UNR;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            // planes that touch the group's columns: [n_lo, n_hi)
+            int n_lo = N, n_hi = 0;
+            bool any_out = false;
+            Chunk k;
+            for (int c0 = 0; c0 < N; c0 += 64) {
+                load_chunk(g, c0, k);
+                const int cn = min(64, N - c0);
+                const uint64_t valid = cn == 64 ? ~0ull : ((1ull << cn) - 1);
+                const uint64_t act = valid & ~k.bout;
+                any_out = any_out || k.bout != 0;
+                if (act) {
+                    n_lo = min(n_lo, c0 + (int)__builtin_ctzll(act));
+                    n_hi = max(n_hi, c0 + 64 - (int)__builtin_clzll(act));
+                }
             }
-            interp(g, vv, wlo, whi, d);
-            if (op) store_f32x4<NT>(op + (int64_t)li * ostep + xcol(g), f32x4{d[0], d[1], d[2], d[3]});
+            // an all-OUT plane is zero at every column of the group
+            if (any_out) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
+            }
+            if (n_lo >= n_hi) continue;
+            // the pipelined range: whole groups of U planes, aligned (so a
+            // group never spans two chunks), rows at a stack end excluded
+            const int lo = n_lo + ((first_special == 0 && n_lo == 0) ? 1 : 0);
+            const int hi = n_hi - ((last_special == N - 1 && n_hi == N) ? 1 : 0);
+            int mlo = (lo + U - 1) / U * U, mhi = hi / U * U;
+            if (mlo >= mhi) mlo = mhi = n_hi;
+            singles(g, n_lo, mlo, k);
+            if (mlo < mhi) {
+                Chunk cur, nxt;
+                load_chunk(g, mlo & ~63, cur);
+                nxt = cur;
+                if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
+                Win A[U], B[U];
+                int va[U], vb[U];
+                issue_group<U>(g, mlo, false, cur, nxt, A, va);
+#pragma unroll
+                for (int u = 0; u < U; ++u) A[u].settle();
+                int n = mlo;
+                // two groups per trip, alternating the window registers
+                while (true) {
+                    bool rep = n + U >= mhi;
+                    issue_group<U>(g, rep ? mhi - 1 : n + U, rep, cur, nxt, B, vb);
+                    compute_group<U>(g, n, cur, A, va);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) B[u].settle();
+                    n += U;
+                    if (n >= mhi) break;
+                    if (n >= cur.c0 + 64) {
+                        cur = nxt;
+                        if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
+                    }
+                    rep = n + U >= mhi;
+                    issue_group<U>(g, rep ? mhi - 1 : n + U, rep, cur, nxt, A, va);
+                    compute_group<U>(g, n, cur, B, vb);
+#pragma unroll
+                    for (int u = 0; u < U; ++u) A[u].settle();
+                    n += U;
+                    if (n >= mhi) break;
+                    if (n >= cur.c0 + 64) {
+                        cur = nxt;
+                        if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
+                    }
+                }
+                k = cur;
+            }
+            singles(g, mhi, n_hi, k);
         }
     }
 
     __device__ __forceinline__ void run() {
         if (!alive) return;
-        for (int c0 = 0; c0 < N; c0 += 64) {
-            const int cn = min(64, N - c0);
-            chunk(c0);
-            const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < cn);
-            const bool special = (first_special >= c0 && first_special < c0 + cn) ||
-                                 (last_special >= c0 && last_special < c0 + cn);
-            const TIn *rp = rp0 + (int64_t)c0 * rstep;
-            float *op = op0 ? op0 + (int64_t)c0 * ostep : nullptr;
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int cl = cls_of(ls0, g);
-                const uint64_t bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
-                const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
-                if (special) {
-                    slow_loop(g, c0, cn, rp, op);
-                } else if (bout == valid) {
-                    // padding: zero output, nothing added to the sum
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
-                    if (op) {
-                        float *o = op + xcol(g);
-                        for (int li = 0; li < cn; ++li) {
-                            if ((li & 3) == 0) pace_until(t0, taug, pace_pos(g, c0, cn, li));
-                            store_f32x4<NT>(o, f32x4{0.0f, 0.0f, 0.0f, 0.0f});
-                            o += ostep;
-                        }
-                    }
-                } else if (bin == valid) {
-                    if (op) pipe_loop<UNR, false, true>(g, c0, cn, rp, op);
-                    else pipe_loop<UNR, false, false>(g, c0, cn, rp, op);
-                } else {
-                    if (op) pipe_loop<UNR, true, true>(g, c0, cn, rp, op);
-                    else pipe_loop<UNR, true, false>(g, c0, cn, rp, op);
-                }
-            }
-        }
+        if constexpr (VOL)
+            run_volume();
+        else
+            run_projections();
 #pragma unroll
         for (int g = 0; g < G; ++g) {
 #pragma unroll
@@ -694,29 +885,55 @@ __global__ __launch_bounds__(BLOCK) void k_forward_scalar(FwdArgs<TIn> a, int ti
     fwd_tile_scalar<TIn, BLOCK, J, NT>(a, r, (int64_t)xt * (BLOCK * J));
 }
 
-template <typename TIn, int BLOCK, int G, int UNR, bool NT>
+// Column tile of rank k in middle-out order over T tiles: the centre tile,
+// then alternately right and left of it.  A bijection on [0, T).
+__device__ __forceinline__ int middle_out(int k, int T) {
+    const int c = (T - 1) / 2;
+    return k == 0 ? c : ((k & 1) ? c + (k + 1) / 2 : c - k / 2);
+}
+
+// Block b of a plain launch.  With a volume: row-major tiles (paced launches
+// start workgroups in id order, a batch of resident ones at a time).
+// Without: the tiles of one column rank for every row, ranks middle-out, so
+// the heaviest tiles start first (in a uniform scan a column tile meets the
+// most planes at the frame's centre, the fewest at its ends) and lighter
+// ones fill in behind them.
+template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
 __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x, int64_t b) {
     const int64_t main = (int64_t)a.R * tiles_x;
     if (b < main) {
-        const int r = (int)(b / tiles_x);
-        const int xt = (int)(b - (int64_t)r * tiles_x);
-        VecTile<TIn, BLOCK, G, UNR, NT> vt(a, r, xt);
+        int r, xt;
+        if constexpr (VOL) {
+            r = (int)(b / tiles_x);
+            xt = (int)(b - (int64_t)r * tiles_x);
+        } else {
+            const int k = (int)(b / a.R);
+            r = (int)(b - (int64_t)k * a.R);
+            xt = middle_out(k, tiles_x);
+        }
+        VecTile<TIn, BLOCK, G, UNR, NT, VOL> vt(a, r, xt);
         vt.run();
     } else {
         fwd_edge_lane<TIn, UNR, NT>(a, (int)((b - main) * BLOCK + threadIdx.x));
     }
 }
 
-// One group per lane with a shallow plane pipeline (UNR <= 2) is built for
-// 8 wavefronts per SIMD, so that a 512-row stack's tiles are all resident at
-// once (plane pacing then holds every wavefront of the launch to one
-// schedule).
-constexpr int vec_waves_per_eu(int g, int unr) { return g == 1 && unr <= 2 ? 8 : 1; }
+// One group per lane with a shallow plane pipeline (UNR <= 2) writing the
+// volume is built for 8 wavefronts per SIMD, so that a 512-row stack's tiles
+// are all resident at once (plane pacing then holds every wavefront of the
+// launch to one schedule).  Launches without a volume are not paced; with
+// one group per lane they are built for 7 wavefronts per SIMD (72
+// registers, room for a 4-plane pipeline), so the 512-row stack's 7168
+// tiles are again all resident at once; with two groups for 6.
+constexpr int vec_waves_per_eu(int g, int unr, bool vol) {
+    return vol ? (g == 1 && unr <= 2 ? 8 : 1) : (g == 1 ? 7 : 6);
+}
 
-template <typename TIn, int BLOCK, int G, int UNR, bool NT>
-__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR)) void k_forward_vec(FwdArgs<TIn> a,
-                                                                              int tiles_x) {
-    fwd_vec_block<TIn, BLOCK, G, UNR, NT>(a, tiles_x, xcd_remap(blockIdx.x, gridDim.x));
+template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR, VOL)) void k_forward_vec(
+    FwdArgs<TIn> a, int tiles_x) {
+    fwd_vec_block<TIn, BLOCK, G, UNR, NT, VOL>(
+        a, tiles_x, VOL ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
 }
 
 // Job record of the persistent ragged-batch kernel (device-resident table).
@@ -734,10 +951,11 @@ struct JobDev {
 
 // Persistent launch: workgroups stride over the concatenated tile lists of
 // all jobs (job-major).  Each tile runs exactly the code of the plain launch
-// for that job, so outputs are bitwise equal.
-template <int BLOCK, int PT, int UNR, bool NT>
-__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR)) void k_forward_jobs(const JobDev *__restrict__ jobs,
-                                                        int n_jobs, int64_t total_tiles) {
+// for that job, so outputs are bitwise equal.  One launch covers jobs that
+// all write a volume (VOL) or all do not.
+template <int BLOCK, int PT, int UNR, bool NT, bool VOL>
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL)) void k_forward_jobs(
+    const JobDev *__restrict__ jobs, int n_jobs, int64_t total_tiles) {
     const int64_t grid = gridDim.x;
     const int64_t me = blockIdx.x;
     for (int64_t base = 0; base < total_tiles; base += grid) {
@@ -773,7 +991,7 @@ __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR)) void
         const int64_t lt = t - jb.tile_begin;
         if constexpr (PT >= 4) {
             if (jb.vec) {
-                fwd_vec_block<uint16_t, BLOCK, PT / 4, UNR, NT>(a, jb.tiles_x, lt);
+                fwd_vec_block<uint16_t, BLOCK, PT / 4, UNR, NT, VOL>(a, jb.tiles_x, lt);
                 continue;
             }
         }

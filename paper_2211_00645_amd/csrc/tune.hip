@@ -119,12 +119,14 @@ namespace {
 // always a candidate.  Without a volume nothing is paced: groups and
 // pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
-    std::vector<dsk_tune> c{kDefaultTune};
     if (!paced) {
+        std::vector<dsk_tune> c{kDefaultProjTune};
         for (int pt : {4, 8})
-            for (int u : {2, 4}) c.push_back(dsk_tune{64, pt, 1, u, 0, 0});
+            for (int u : {2, 4})
+                if (pt != 4 || u != 4) c.push_back(dsk_tune{64, pt, 1, u, 0, 0});
         return c;
     }
+    std::vector<dsk_tune> c{kDefaultTune};
     for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5800, 5900, 6000})
         c.push_back(dsk_tune{64, 4, 1, 2, 0, pace});
     for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
@@ -201,6 +203,58 @@ size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &scor
     return pick;
 }
 
+// Steady-state check of the front runners.  Short bursts of a shape that
+// follow other shapes can hold a pace that a long run of that shape alone
+// cannot (the run settles and then falls off the cliff), and a stream of
+// stacks is a long run.  The candidates within kSteadyBand of the best
+// burst score are each run kSteady times back to back, kSteadyRounds
+// rounds in turn, and re-scored by their mean time per launch.
+constexpr double kSteadyBand = 1.03;
+constexpr int kSteady = 12, kSteadyRounds = 2, kSteadyMax = 4;
+
+int steady_scores(const std::vector<dsk_tune> &cand, const std::vector<double> &score,
+                  const void *in, int in_is_f32, dsk_dims d, const double *offs, double shift,
+                  int64_t origin, float *vol, float *psum, float *pmax, int64_t width,
+                  hipStream_t s, std::vector<dsk_tune> *fc, std::vector<double> *fs) {
+    double lo = score[0];
+    for (double v : score) lo = v < lo ? v : lo;
+    std::vector<size_t> idx;
+    for (size_t i = 0; i < cand.size(); ++i)
+        if (score[i] <= lo * kSteadyBand) idx.push_back(i);
+    std::sort(idx.begin(), idx.end(), [&](size_t x, size_t y) { return score[x] < score[y]; });
+    if (idx.size() > (size_t)kSteadyMax) idx.resize(kSteadyMax);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = DSK_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) st = DSK_EHIP;
+    std::vector<double> sum(idx.size(), 0.0);
+    for (int round = 0; round < kSteadyRounds && st == DSK_OK; ++round) {
+        for (size_t j = 0; j < idx.size() && st == DSK_OK; ++j) {
+            const dsk_tune &t = cand[idx[j]];
+            // one untimed launch settles the shape after the previous one
+            st = launch_forward(in, in_is_f32, d, offs, shift, origin, vol, psum, pmax, width, t, s);
+            if (st == DSK_OK && hipEventRecord(e0, s) != hipSuccess) st = DSK_EHIP;
+            for (int k = 0; k < kSteady && st == DSK_OK; ++k)
+                st = launch_forward(in, in_is_f32, d, offs, shift, origin, vol, psum, pmax, width,
+                                    t, s);
+            if (st == DSK_OK && hipEventRecord(e1, s) != hipSuccess) st = DSK_EHIP;
+            if (st == DSK_OK && hipEventSynchronize(e1) != hipSuccess) st = DSK_EHIP;
+            float ms = 0.0f;
+            if (st == DSK_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = DSK_EHIP;
+            sum[j] += ms / kSteady;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st != DSK_OK) return st;
+    fc->clear();
+    fs->clear();
+    for (size_t j = 0; j < idx.size(); ++j) {
+        fc->push_back(cand[idx[j]]);
+        fs->push_back(sum[j] / kSteadyRounds);
+    }
+    return DSK_OK;
+}
+
 }  // namespace
 
 extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
@@ -230,9 +284,15 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
                                        shift_px, origin, vol, psum, pmax, out_width, stream,
                                        &score);
         if (st != DSK_OK) return st;
-        const size_t bi = choose(cand, score);
-        best = cand[bi];
-        best_ms = score[bi];
+        std::vector<dsk_tune> front;
+        std::vector<double> fscore;
+        const int st2 = steady_scores(cand, score, in, in_is_f32 ? 1 : 0, d, offsets_dev,
+                                      shift_px, origin, vol, psum, pmax, out_width, stream,
+                                      &front, &fscore);
+        if (st2 != DSK_OK) return st2;
+        const size_t bi = choose(front, fscore);
+        best = front[bi];
+        best_ms = fscore[bi];
         tune_cache_store(key, best, best_ms, 0);
     }
     {

@@ -125,7 +125,7 @@ extern "C" int dsk_view_u16(const uint16_t *in, dsk_dims d, double shear_px, dou
     float *ps = (float *)workspace;
     float *pm = ps + (size_t)d.rows * (size_t)proj_width;
     st = launch_forward(in, 0, d, nullptr, shear_px, origin, nullptr, vsum ? ps : nullptr,
-                        vmax ? pm : nullptr, proj_width, kDefaultTune, stream);
+                        vmax ? pm : nullptr, proj_width, kDefaultProjTune, stream);
     if (st != DSK_OK) return st;
     if (vsum) launch_stretch(ps, d.rows, proj_width, stretch, vsum, view_width, stream);
     if (vmax) launch_stretch(pm, d.rows, proj_width, stretch, vmax, view_width, stream);

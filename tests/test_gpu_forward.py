@@ -105,6 +105,10 @@ def test_every_launch_shape_is_bitwise_identical(cfg1):
         o = dsk.deskew(x, offsets=off, tune=t)
         for k in ("vol", "psum", "pmax"):
             assert torch.equal(o[k], base[k]), (t, k)
+        # the projections-only pass (its own loop) gives the same projections
+        p = dsk.deskew(x, offsets=off, tune=t, vol=False)
+        for k in ("psum", "pmax"):
+            assert torch.equal(p[k], base[k]), (t, k, "projections only")
     # the uniform-scan path (offsets computed on the device) matches too
     o = dsk.deskew(x, 30.0, 0.4, 0.115)
     for k in ("vol", "psum", "pmax"):
@@ -153,6 +157,8 @@ RAGGED = [
     (4, 4, 7, "frac", 9),          # rows*cols % 4 == 0, W odd
     (9, 12, 300, "neg", 10),       # vector kernel with negative offsets
     (2, 2, 2, "frac", 11),         # tiny stack: scalar kernel
+    (150, 6, 400, "shuffle", 12),  # offsets out of order: padding planes between others
+    (200, 8, 300, "frac", 13),     # several 64-plane chunks, partial last chunk
 ]
 
 
@@ -170,6 +176,8 @@ def _offsets(kind, n, seed):
         return oracle.offsets_uniform(n, 40.0)
     if kind == "zero":
         return np.zeros(n)
+    if kind == "shuffle":
+        return rng.permutation(n).astype(np.float64) * 5.3 + rng.uniform(0, 1, n)
     raise ValueError(kind)
 
 
@@ -186,8 +194,11 @@ def test_ragged_shapes(n, r, c, kind, seed, dtype):
     off = _offsets(kind, n, seed)
     ref = oracle.deskew(sn, off)
     out = dsk.deskew(st.to(DEV), offsets=off)
+    proj = dsk.deskew(st.to(DEV), offsets=off, vol=False)
     torch.cuda.synchronize()
     assert (out["origin"], out["width"]) == (ref["origin"], ref["width"])
+    for k in ("psum", "pmax"):
+        assert torch.equal(proj[k], out[k]), f"projections-only {k}"
     v = _to_np(out["vol"])
     if kind in ("int", "zero"):
         assert v.tobytes() == ref["vol"].tobytes()
@@ -238,6 +249,12 @@ def test_live_scale_config2_sampled_rows():
     for k in ("vol", "psum", "pmax"):
         assert torch.equal(out[k], dflt[k]), k
     del dflt
+    _say("forward: config 2 projections only")
+    proj = dsk.deskew(st, 35.0, 0.4, 0.115, vol=False)
+    torch.cuda.synchronize()
+    for k in ("psum", "pmax"):
+        assert torch.equal(proj[k], out[k]), f"projections-only {k}"
+    del proj
     torch.cuda.empty_cache()
     rows = [0, 1, 137, 255, 256, 400, 511]
     sn = st.cpu().numpy()
@@ -257,6 +274,25 @@ def test_live_scale_config2_sampled_rows():
     tot_in = float(st.to(torch.int64).sum())
     tot_out = float(out["psum"].double().sum())
     assert tot_out == pytest.approx(tot_in, rel=1e-6)
+
+
+@pytest.mark.parametrize("step", [0.0, 0.4])
+def test_signed_stack_maximum(step):
+    """Float32 stack of negative values: with zero shift there is no
+    padding, so the maximum projection is the largest (negative) value;
+    with a shift, columns that some image does not cover get the padding's
+    0.  Both passes agree with the oracle."""
+    n, r, c = 70, 5, 96
+    st = -1.0 - synth.blob_stack((n, r, c), 8, 14, dtype="f32")
+    off = oracle.offsets_uniform(n, oracle.shift_px(35.0, step, 0.115))
+    ref = oracle.deskew(st.numpy(), off)
+    for vol in (True, False):
+        out = dsk.deskew(st.to(DEV), offsets=off, vol=vol)
+        torch.cuda.synchronize()
+        pm = _to_np(out["pmax"])
+        _check_close(pm, ref["pmax"], np.abs(ref["pmax"]).astype(np.float64), f"pmax vol={vol}")
+        if step == 0.0:
+            assert (pm < 0).all()
 
 
 def test_invalid_arguments_raise():
