@@ -44,13 +44,15 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the kernel as it stands (else None)."""
-    if not os.path.exists(PMC_SUMMARY):
+def measured_traffic(summary=None):
+    """HBM bytes per launch from a committed rocprofv3 counter summary (the
+    forward's by default), if it was taken on the kernel as it stands (else
+    None)."""
+    summary = summary or PMC_SUMMARY
+    if not os.path.exists(summary):
         return None
     vals = {}
-    with open(PMC_SUMMARY) as fh:
+    with open(summary) as fh:
         for line in fh:
             if line.startswith("- ") and ":" in line:
                 k, v = line[2:].split(":", 1)
@@ -215,24 +217,37 @@ def _batch_case(torch, dsk, synth, jobs, seed0, label):
         del r
     torch.cuda.empty_cache()
 
+    # each job's frame in the shape the single-stack tuner picks for it (the
+    # batch tuner already measured these frames, so this only looks them up)
+    job_tunes = [dsk.autotune(s, *g, out=o, reps=3)["tune"] for s, g, o in zip(stacks, geoms, outs)]
+
     def plain():
         for s, g, o in zip(stacks, geoms, outs):
             dsk.deskew(s, *g, out=o)
+
+    def plain_tuned():
+        for s, g, o, t in zip(stacks, geoms, outs, job_tunes):
+            dsk.deskew(s, *g, out=o, tune=t)
     plain()
-    t_graph, t_plain = [], []
+    plain_tuned()
+    t_graph, t_plain, t_tuned = [], [], []
     for _ in range(6):
         t_graph.append(_one_ms(torch, b.launch))
         t_plain.append(_one_ms(torch, plain))
+        t_tuned.append(_one_ms(torch, plain_tuned))
     ms_graph, ms_plain = statistics.median(t_graph), statistics.median(t_plain)
+    ms_tuned = statistics.median(t_tuned)
     b.close()
     del b, outs, stacks
     torch.cuda.empty_cache()
     return {"workload": label,
             "graph_ms": ms_graph, "plain_launches_ms": ms_plain,
-            "speedup": ms_plain / ms_graph, "gbs_graph": alg / ms_graph / 1e6,
+            "speedup": ms_plain / ms_graph, "plain_tuned_launches_ms": ms_tuned,
+            "speedup_vs_tuned": ms_tuned / ms_graph, "gbs_graph": alg / ms_graph / 1e6,
             "voxels_per_s_graph": vox / ms_graph * 1e3, "algorithmic_bytes": alg,
             "bitwise_equal": same, "mode": mode, "tune": tune,
-            "timing": "graph replays and plain launch sequences alternate, 6 each, on the "
+            "timing": "graph replays, plain launches in the library default shape and "
+                      "plain launches in each job's tuned shape alternate, 6 each, on the "
                       "same output buffers; medians"}
 
 
@@ -262,6 +277,30 @@ def _b2b_ms(torch, fn, reps):
     e1.record()
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+PROJ_PMC_SUMMARY = os.path.join(ROOT, "profiles", "projections_512x512x2048_pmc.md")
+
+
+def bench_projections(torch, dsk, stack):
+    """The live view alone (Fig. 2d): sum and maximum projections of the
+    512 x 512 x 2048 stack without writing the volume, in the library default
+    shape, calls back to back.  One launch reads the stack once and writes
+    the two projections."""
+    w, b = dsk.plan((N, R, C), shift=dsk.shift_px(ANGLE, STEP, PIXEL))
+    out = {"psum": torch.empty((R, w), dtype=torch.float32, device=stack.device),
+           "pmax": torch.empty((R, w), dtype=torch.float32, device=stack.device)}
+    reps = 50
+    ms = _b2b_ms(torch, lambda: dsk.deskew(stack, ANGLE, STEP, PIXEL, vol=False, out=out), reps)
+    alg = 2 * N * R * C + 8 * R * w
+    achieved = alg / (ms * 1e-3) / 1e9
+    return {"workload": "sum + max projections only (no volume), 512x512x2048 uint16 stack, "
+                        "35 deg, library default launch shape",
+            "ms": ms, "algorithmic_bytes": alg, "input_voxels_per_s": N * R * C / ms * 1e3,
+            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "traffic": measured_traffic(PROJ_PMC_SUMMARY)},
+            "timing": f"{reps} launches back to back between two events on the launch stream"}
 
 
 def bench_autograd(torch, dsk, synth):
@@ -450,9 +489,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
-    ap.add_argument("--extras", default="batch,autograd,view,affine,rolling,sizes,serving",
-                    help="comma list of extra measurements (batch, autograd, view, affine, "
-                         "rolling, sizes, serving) or none")
+    ap.add_argument("--extras",
+                    default="projections,batch,autograd,view,affine,rolling,sizes,serving",
+                    help="comma list of extra measurements (projections, batch, autograd, view, "
+                         "affine, rolling, sizes, serving) or none")
     ap.add_argument("--tune", default="auto",
                     help="launch shape of the timed forward: auto (the library's tuner, run "
                          "once before the warm-up) or default (the library default)")
@@ -532,6 +572,15 @@ def main():
     log(f"kernel avg {avg_kern_ms:.4f} ms (median {statistics.median(kern_ms):.4f}); "
         f"{achieved:.0f} GB/s; wall {ms_per_step:.4f} ms/step")
 
+    extras = [e for e in args.extras.split(",") if e and e != "none"]
+    ext = {}
+    if "projections" in extras:
+        log("projections only (live view)")
+        ext["projections"] = bench_projections(torch, dsk, stack)
+        pr = ext["projections"]
+        log(f"projections: {pr['ms']:.4f} ms, {pr['roofline']['achieved']:.0f} GB/s "
+            f"({pr['roofline']['frac']:.3f} of peak)")
+
     copy_gbs = copy_ceiling(torch)
     log(f"device copy ceiling {copy_gbs:.0f} GB/s")
 
@@ -548,15 +597,14 @@ def main():
     del stack
     torch.cuda.empty_cache()
 
-    extras = [e for e in args.extras.split(",") if e and e != "none"]
-    ext = {}
     if "batch" in extras:
         log("batch: 64 ragged stacks")
         ext["batch"] = bench_batch(torch, dsk, synth)
         bb, bs = ext["batch"], ext["batch"]["small_stacks"]
         log(f"batch: graph {bb['graph_ms']:.2f} ms ({bb['mode']}) vs plain "
-            f"{bb['plain_launches_ms']:.2f} ms; small stacks: graph {bs['graph_ms']:.3f} ms "
-            f"({bs['mode']}) vs plain {bs['plain_launches_ms']:.3f} ms")
+            f"{bb['plain_launches_ms']:.2f} ms, plain tuned {bb['plain_tuned_launches_ms']:.2f} "
+            f"ms; small stacks: graph {bs['graph_ms']:.3f} ms ({bs['mode']}) vs plain "
+            f"{bs['plain_launches_ms']:.3f} ms, plain tuned {bs['plain_tuned_launches_ms']:.3f} ms")
     if "autograd" in extras:
         log("autograd: forward + backward")
         ext["autograd"] = bench_autograd(torch, dsk, synth)
