@@ -433,7 +433,7 @@ def bench_size_sweep(torch, dsk, synth):
     return res
 
 
-def bench_serving(torch, dsk, synth, n_req, rate, sweep=(), sweep_s=10.0, n_live=400):
+def bench_serving(torch, dsk, synth, n_req, rate, sweep=(), sweep_s=6.0, n_live=400):
     """Poisson arrivals of 2-channel stacks (100-400 x 512/1024 x 1024/2048),
     200 GB budget; continuous batching vs one stack at a time.  The live run
     has ``n_live`` requests (its p99 is then the 4th-worst latency of 400,
@@ -469,14 +469,18 @@ def bench_serving(torch, dsk, synth, n_req, rate, sweep=(), sweep_s=10.0, n_live
             f"{res[mode]['latency_p99_ms']:.2f} ms; plain p99 "
             f"{res[mode + '_plain']['latency_p99_ms']:.2f} ms")
     if sweep:
+        # each arrival rate: the same trace served and one stack at a time
         res["sweep"] = {}
         for lam in sweep:
-            n = int(max(20, round(lam * sweep_s)))
+            n = int(max(30, round(lam * sweep_s)))
             tr = synth.serving_trace(n, lam, 11)
             sch = sv.Scheduler(ex, budget, n_slots=4, max_batch=8, on_complete=consume)
-            res["sweep"][f"{lam:g}Hz"] = dict(sv.summarize(sch.run(sv.make_requests(tr))),
-                                               launches=sch.launches)
-            log(f"serving {lam:g} Hz x {n}: p99 {res['sweep'][f'{lam:g}Hz']['latency_p99_ms']:.2f} ms")
+            served = dict(sv.summarize(sch.run(sv.make_requests(tr))), launches=sch.launches)
+            plain = sv.summarize(sv.run_plain(ex, sv.make_requests(tr), on_complete=consume))
+            res["sweep"][f"{lam:g}Hz"] = {"requests": n, "served": served, "plain": plain}
+            log(f"serving {lam:g} Hz x {n}: p99 {served['latency_p99_ms']:.2f} ms "
+                f"(max {served['latency_max_ms']:.2f}); plain p99 {plain['latency_p99_ms']:.2f} "
+                f"(max {plain['latency_max_ms']:.2f})")
     del pool, ex
     torch.cuda.empty_cache()
     return res
@@ -500,10 +504,10 @@ def main():
     ap.add_argument("--serve-live-requests", type=int, default=400,
                     help="requests of the live (Poisson) run")
     ap.add_argument("--serve-rate", type=float, default=50.0)
-    ap.add_argument("--serve-sweep", default="",
-                    help="comma list of arrival rates (Hz) to also run live for about "
-                         "--serve-seconds each, e.g. 5,10,20,50")
-    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-sweep", default="5,10,20,50",
+                    help="comma list of arrival rates (Hz) also run live, served and one "
+                         "stack at a time, for about --serve-seconds each ('' to skip)")
+    ap.add_argument("--serve-seconds", type=float, default=6.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}): the library has no "

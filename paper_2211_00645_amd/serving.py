@@ -73,7 +73,13 @@ def request_bytes(req: Request, width: int, keep_volume: bool = True) -> int:
 
 
 class RealClock:
+    """Wall time in seconds since the clock was started (request arrival
+    times are relative to that origin)."""
+
     def __init__(self):
+        self.t0 = time.perf_counter()
+
+    def start(self):
         self.t0 = time.perf_counter()
 
     def now(self) -> float:
@@ -90,6 +96,9 @@ class FakeClock:
 
     def __init__(self):
         self.t = 0.0
+
+    def start(self):
+        pass
 
     def now(self) -> float:
         return self.t
@@ -123,7 +132,11 @@ class Scheduler:
         self.space_waits = 0
 
     def run(self, requests: List[Request]) -> List[Request]:
+        """Serve ``requests`` (arrival times relative to the start of the
+        run: the clock starts once the loop is about to begin, after the
+        garbage-collector pause's collection)."""
         with gc_paused():
+            self.clock.start()
             return self._run(requests)
 
     def _run(self, requests: List[Request]) -> List[Request]:
@@ -246,6 +259,7 @@ def run_plain(executor, requests: List[Request], clock=None, on_complete=None) -
 
 def _run_plain(executor, requests: List[Request], clock=None, on_complete=None) -> List[Request]:
     clock = clock or RealClock()
+    clock.start()
     out = []
     for r in sorted(requests, key=lambda q: q.t_arrival):
         r.width = executor.width(r)

@@ -190,3 +190,35 @@ def test_on_complete_sees_every_request_once_after_it_is_done():
     run_plain(MockExecutor(clk2, s_per_byte=1e-9), _reqs([0.0, 0.1]), clock=clk2,
               on_complete=hook)
     assert seen == [0, 1]
+
+
+def test_clock_starts_when_the_loop_starts():
+    """Arrival times count from the start of the run itself, not from the
+    scheduler's construction or the collector pause before the loop."""
+    import time
+    from paper_2211_00645_amd.serving import RealClock
+
+    class Clk(FakeClock):
+        def __init__(self):
+            super().__init__()
+            self.started = 0
+            self.read_before_start = False
+
+        def start(self):
+            self.started += 1
+
+        def now(self):
+            if not self.started:
+                self.read_before_start = True
+            return super().now()
+
+    clk = Clk()
+    Scheduler(MockExecutor(clk), budget_bytes=10**12, clock=clk).run(_reqs([0.0, 0.1]))
+    assert clk.started == 1 and not clk.read_before_start
+    clk2 = Clk()
+    run_plain(MockExecutor(clk2), _reqs([0.0, 0.1]), clock=clk2)
+    assert clk2.started == 1 and not clk2.read_before_start
+    rc = RealClock()
+    time.sleep(0.03)
+    rc.start()
+    assert rc.now() < 0.02
