@@ -112,12 +112,12 @@ using namespace dsk;
 
 namespace {
 
-// Shapes the single-stack tuner times.  With a volume: one and two 4-column
-// groups per lane, each unpaced and paced over the range where the cliff
-// lies on the frames measured (5000-6000 GB/s; one group per lane in 100
-// GB/s steps from 5400, where most frames put it); the default shape is
-// always a candidate.  Without a volume nothing is paced: groups and
-// pipeline depth only.
+// Shapes the single-stack tuner times.  With a volume: one 4-column group
+// per lane with a 2- or 4-plane pipeline, and two groups per lane, each
+// unpaced and paced over the range where the cliff lies on the frames
+// measured (5000-6000 GB/s; one group per lane in 100 GB/s steps from 5400,
+// where most frames put it); the default shape is always a candidate.
+// Without a volume nothing is paced: groups and pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
     if (!paced) {
         std::vector<dsk_tune> c{kDefaultProjTune};
@@ -127,8 +127,13 @@ std::vector<dsk_tune> fwd_candidates(bool paced) {
         return c;
     }
     std::vector<dsk_tune> c{kDefaultTune};
-    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5800, 5900, 6000})
+    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5700, 5900, 6000})
         c.push_back(dsk_tune{64, 4, 1, 2, 0, pace});
+    // a 4-plane pipeline keeps more reads in flight where tiles are few (a
+    // float32 stack of 256 x 512 x 1024 into 1793 columns: 0.308 ms at 5400
+    // against 0.334 for the best 2-plane shape)
+    for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
+        c.push_back(dsk_tune{64, 4, 1, 4, 0, pace});
     for (int pace : {0, 5000, 5200, 5400, 5600, 5800, 6000})
         c.push_back(dsk_tune{64, 8, 1, 2, 0, pace});
     return c;
@@ -188,9 +193,8 @@ int time_candidates(const std::vector<dsk_tune> &cand, int reps, const void *in,
 }
 
 // The choice: among the candidates within kMargin of the fastest, the one
-// paced slowest (unpaced first) -- the cliff lies just above the fastest
-// pace, and a gain inside the timing noise is not worth standing on its
-// edge.
+// paced slowest (unpaced first) -- a gain inside the timing noise is not
+// worth a faster pace.
 constexpr double kMargin = 1.005;
 
 size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &score) {
@@ -200,6 +204,31 @@ size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &scor
     size_t pick = best;
     for (size_t i = 0; i < cand.size(); ++i)
         if (score[i] <= score[best] * kMargin && cand[i].pace_gbs < cand[pick].pace_gbs) pick = i;
+    return pick;
+}
+
+// The same shape paced at least kStepDown GB/s lower (the highest such
+// candidate pace), or cand.size() for an unpaced shape or when none is
+// lower.  The chosen pace is stepped down once more: a pace the device
+// holds for every launch while tuning can fail in the runs that follow, on
+// some devices for every launch, on others for some launches only (on the
+// 512x2048 frame, 6000 GB/s: 0.827 ms in the tuner's runs and 0.90-0.97 ms
+// after; 5900 GB/s: 0.839 ms on two devices, on a third a third of its
+// launches at 0.93-0.98 ms; 5800 held on every device measured).  Falling
+// off costs 10-15%, the step about 3%.
+constexpr int kStepDown = 200;
+
+size_t step_down(const std::vector<dsk_tune> &cand, const dsk_tune &t) {
+    size_t pick = cand.size();
+    if (t.pace_gbs <= 0) return pick;
+    for (size_t i = 0; i < cand.size(); ++i) {
+        const dsk_tune &c = cand[i];
+        if (c.block != t.block || c.per_thread != t.per_thread || c.unroll != t.unroll ||
+            c.nt_store != t.nt_store || c.wg_per_cu != t.wg_per_cu || c.pace_gbs <= 0 ||
+            c.pace_gbs > t.pace_gbs - kStepDown)
+            continue;
+        if (pick == cand.size() || c.pace_gbs > cand[pick].pace_gbs) pick = i;
+    }
     return pick;
 }
 
@@ -293,6 +322,11 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
         const size_t bi = choose(front, fscore);
         best = front[bi];
         best_ms = fscore[bi];
+        const size_t di = step_down(cand, best);
+        if (di < cand.size()) {
+            best = cand[di];
+            best_ms = score[di];
+        }
         tune_cache_store(key, best, best_ms, 0);
     }
     {
