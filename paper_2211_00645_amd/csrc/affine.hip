@@ -108,8 +108,17 @@ struct RingArgs {
 // look-ahead.  The ring has 32 rows plus a copy of row 0 after row 31, so
 // the two images a voxel needs are always in consecutive rows.  The host
 // keeps every u within +-1e9, so floors fit an int.
-template <typename TIn, int YQ, int AHEAD>
+//
+// WIDE (YQ = 4, columns a multiple of 4, volume 16-byte aligned): the four
+// y values of a step go to four groups of 16 lanes, each lane computing 4
+// adjacent columns of its y and storing them with one 16-byte store.  A
+// lane per column would store 4 bytes per lane per y, and then the
+// address/data path of the stores, not memory, bounds the kernel (measured
+// on 512x512x2048: texture data unit busy 87% of the time, 3.5 TB/s); a
+// 16-byte store moves four times the bytes per store instruction.
+template <typename TIn, int YQ, int AHEAD, bool WIDE = false>
 __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
+    static_assert(!WIDE || YQ == 4, "the wide layout is 4 y values x 16 lanes");
     constexpr int NF = YQ == 1 ? 1 : 2;        // fetches per step
     __shared__ float ring[33 * 64];
     const AffArgs<TIn> &a = ra.a;
@@ -123,6 +132,11 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
     const int ze = zb + 63 < a.C ? zb + 63 : a.C - 1;
     const bool zok = zb + lane < a.C;
     const int zc = zok ? zb + lane : ze;       // the column this lane reads and writes
+    // WIDE: this lane's y within a step and its 4 columns (lanes past the
+    // last group repeat it: identical values to identical addresses)
+    const int yq = lane >> 4;
+    const int ngrp = (ze - zb + 1) / 4;
+    const int zq = zb + 4 * ((lane & 15) < ngrp ? (lane & 15) : ngrp - 1);
     const int64_t y_lo = yc * ra.ychunk;
     const int64_t y_hi = (y_lo + ra.ychunk < a.ny ? y_lo + ra.ychunk : a.ny);
     const int ny_c = (int)(y_hi - y_lo);
@@ -135,6 +149,9 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
     const int64_t y_first = up ? y_lo : y_hi - 1;
     const double ds = fabs(a.uy);
     const double uzl = __dmul_rn((double)zc, a.uz);
+    double uzq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uzq[i] = WIDE ? __dmul_rn((double)(zq + i), a.uz) : 0.0;
     const double uzb = __dmul_rn((double)zb, a.uz), uze = __dmul_rn((double)ze, a.uz);
     const double uz_min = uzb < uze ? uzb : uze, uz_max = uzb < uze ? uze : uzb;
     auto fl = [](double v) { return (int)floor(v); };
@@ -228,23 +245,61 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
             qn[k][i] = mi;
         }
         have = m;
-        double p = p0;
+        if constexpr (WIDE) {
+            // this lane's y: the same chain of adds as the band's bookkeeping,
+            // picked without a branch (integer selects on the two halves)
+            const double p1 = __dadd_rn(p0, ds), p2 = __dadd_rn(p1, ds), p3 = __dadd_rn(p2, ds);
+            int plo = __double2loint(p0), phi = __double2hiint(p0);
+            plo = yq == 1 ? __double2loint(p1) : plo;
+            phi = yq == 1 ? __double2hiint(p1) : phi;
+            plo = yq == 2 ? __double2loint(p2) : plo;
+            phi = yq == 2 ? __double2hiint(p2) : phi;
+            plo = yq == 3 ? __double2loint(p3) : plo;
+            phi = yq == 3 ? __double2hiint(p3) : phi;
+            const double p = __hiloint2double(phi, plo);
+            // all ring reads of the step before any is used, so their
+            // latencies overlap
+            int ri[4];
+            float wl[4], wh[4], lo[4], hi[4], v[4];
 #pragma unroll
-        for (int i = 0; i < YQ; ++i) {
-            if (i) p = __dadd_rn(p, ds);
-            const double u = __dsub_rn(p, uzl);
-            const double fi = floor(u);
-            const int r = (int)fi & 31;
-            const double f = __dsub_rn(u, fi);
-            // both weights rounded once from FP64 (1 - wlo in FP32 would lose
-            // the relative precision of a small 1 - f)
-            const float wlo = (float)f, whi = (float)__dsub_rn(1.0, f);
-            const float lo = ring[r * 64 + lane];
-            const float hi = ring[r * 64 + 64 + lane];
-            // lanes past the last column repeat the last column's value to
-            // its address: one unconditional store per y
-            if (!tail || j * YQ + i < ny_c) store_f32<true>(orow + zc, fmaf(wlo, hi, whi * lo));
-            orow += ostep;
+            for (int i = 0; i < 4; ++i) {
+                const double u = __dsub_rn(p, uzq[i]);
+                const double fi = floor(u);
+                ri[i] = ((int)fi & 31) * 64 + (zq - zb + i);
+                const double f = __dsub_rn(u, fi);
+                wl[i] = (float)f;
+                wh[i] = (float)__dsub_rn(1.0, f);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                lo[i] = ring[ri[i]];
+                hi[i] = ring[ri[i] + 64];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = fmaf(wl[i], hi[i], wh[i] * lo[i]);
+            if (!tail || j * 4 + yq < ny_c)
+                store_f32x4<true>(orow + (int64_t)yq * ostep + zq, f32x4{v[0], v[1], v[2], v[3]});
+            orow += 4 * ostep;
+        } else {
+            double p = p0;
+#pragma unroll
+            for (int i = 0; i < YQ; ++i) {
+                if (i) p = __dadd_rn(p, ds);
+                const double u = __dsub_rn(p, uzl);
+                const double fi = floor(u);
+                const int r = (int)fi & 31;
+                const double f = __dsub_rn(u, fi);
+                // both weights rounded once from FP64 (1 - wlo in FP32 would
+                // lose the relative precision of a small 1 - f)
+                const float wlo = (float)f, whi = (float)__dsub_rn(1.0, f);
+                const float lo = ring[r * 64 + lane];
+                const float hi = ring[r * 64 + 64 + lane];
+                // lanes past the last column repeat the last column's value
+                // to its address: one unconditional store per y
+                if (!tail || j * YQ + i < ny_c)
+                    store_f32<true>(orow + zc, fmaf(wlo, hi, whi * lo));
+                orow += ostep;
+            }
         }
     };
     const int full = (ny_c / YQ) / AHEAD * AHEAD;   // steps with all YQ y values, whole groups
@@ -313,8 +368,12 @@ extern "C" int dsk_affine_u16(const uint16_t *in, dsk_dims d, dsk_geom g, double
     for (double v : ue) u_ok = u_ok && std::fabs(v) < 1.0e9;
     if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.499 && band4 <= 32.0) {
         const RingArgs<uint16_t> ra{a, ychunk, ztiles};
-        hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4>), dim3((unsigned)blocks), dim3(64), 0,
-                           stream, ra);
+        if (d.cols % 4 == 0 && ((uintptr_t)vol & 15) == 0)
+            hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4, true>), dim3((unsigned)blocks),
+                               dim3(64), 0, stream, ra);
+        else
+            hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4>), dim3((unsigned)blocks), dim3(64),
+                               0, stream, ra);
         return hip_status(hipGetLastError());
     }
     if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.999 && band1 <= 32.0) {

@@ -35,6 +35,8 @@ def test_index_shear_case_is_bitwise():
     ((30, 8, 64), 45.0, -0.3, 0.2),           # reversed scan
     ((1, 5, 40), 35.0, 0.4, 0.115),           # one image
     ((90, 4, 48), 20.0, 0.15, 0.3),           # small step: columns cross several images
+    ((50, 20, 200), 35.0, 0.4, 0.115),        # 4 columns per lane, last column tile partial
+    ((70, 6, 40), 30.0, 0.4, 0.09),           # 4 columns per lane, one partial tile
 ])
 def test_matches_oracle(shape, ang, step, dy):
     st = synth.blob_stack(shape, 20, 5, device=DEV)
