@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdint>
 #include <mutex>
+#include <type_traits>
 
 #include "common.hpp"
 #include "deskew.h"
@@ -275,12 +276,23 @@ int launch_backward(const float *in, const float *gvol, dsk_dims d, const double
     BwdArgs a{in, gvol, gin, (double *)ws, offs, 0.0, (double)origin, width,
               d.planes, d.rows, d.cols, bwd_rows_per_block(d), G};
     const dim3 grid((unsigned)blocks), block(kBwdBlock);
-    if (gin && goff)
-        hipLaunchKernelGGL((k_backward<kBwdBlock, true, true>), grid, block, 0, stream, a);
-    else if (gin)
-        hipLaunchKernelGGL((k_backward<kBwdBlock, true, false>), grid, block, 0, stream, a);
+    // 4 columns per thread when the rows of the stack and of the adjoint
+    // start 16-byte aligned
+    const bool vec = d.cols % 4 == 0 && (!goff || ((uintptr_t)in & 15) == 0) &&
+                     (!gin || ((uintptr_t)gin & 15) == 0) && ((uintptr_t)gvol & 3) == 0;
+    auto go = [&](auto V) {
+        constexpr bool v = decltype(V)::value;
+        if (gin && goff)
+            hipLaunchKernelGGL((k_backward<kBwdBlock, true, true, v>), grid, block, 0, stream, a);
+        else if (gin)
+            hipLaunchKernelGGL((k_backward<kBwdBlock, true, false, v>), grid, block, 0, stream, a);
+        else
+            hipLaunchKernelGGL((k_backward<kBwdBlock, false, true, v>), grid, block, 0, stream, a);
+    };
+    if (vec)
+        go(std::true_type{});
     else
-        hipLaunchKernelGGL((k_backward<kBwdBlock, false, true>), grid, block, 0, stream, a);
+        go(std::false_type{});
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return DSK_EHIP;
     if (goff) {

@@ -1038,7 +1038,7 @@ __device__ __forceinline__ double block_sum(double v, double *lds) {
 // (equal to summing gD[x'] * (S[x'-k-1] - S[x'-k]) over x').
 // Workgroups are plane-major: block = n * G + g covers rows
 // [g * rows_per_block, ...) of plane n.
-template <int BLOCK, bool GIN, bool GOFF>
+template <int BLOCK, bool GIN, bool GOFF, bool VEC>
 __global__ __launch_bounds__(BLOCK) void k_backward(BwdArgs a) {
     __shared__ double lds[BLOCK / 64];
     const int n = blockIdx.x / a.G;
@@ -1054,12 +1054,49 @@ __global__ __launch_bounds__(BLOCK) void k_backward(BwdArgs a) {
         const float *srow = a.in + rowi * C;
         float *orow = nullptr;
         if constexpr (GIN) orow = a.gin + rowi * C;
-        for (int64_t c = threadIdx.x; c < C; c += BLOCK) {
-            const int64_t x = c + pc.k;
-            const float g0 = load_px(grow, x, W);
-            const float g1 = load_px(grow, x + 1, W);
-            if constexpr (GIN) orow[c] = fmaf(pc.whi, g0, pc.wlo * g1);
-            if constexpr (GOFF) part += (double)srow[c] * ((double)g1 - (double)g0);
+        if constexpr (VEC) {
+            // 4 adjacent raw columns per thread: their 5 gradient values
+            // from one 16-byte and one 4-byte load (per pixel where the
+            // window leaves [0, W)), the stack and the adjoint in 16 bytes
+            for (int64_t c = 4 * (int64_t)threadIdx.x; c < C; c += 4 * BLOCK) {
+                const int64_t x = c + pc.k;
+                float gv[5];
+                if (x >= 0 && x + 5 <= W) {
+                    float4 q;
+                    __builtin_memcpy(&q, grow + x, sizeof(q));   // 4-byte aligned
+                    gv[0] = q.x;
+                    gv[1] = q.y;
+                    gv[2] = q.z;
+                    gv[3] = q.w;
+                    gv[4] = grow[x + 4];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 5; ++i) gv[i] = load_px(grow, x + i, W);
+                }
+                if constexpr (GIN) {
+                    f32x4 o;
+                    o.x = fmaf(pc.whi, gv[0], pc.wlo * gv[1]);
+                    o.y = fmaf(pc.whi, gv[1], pc.wlo * gv[2]);
+                    o.z = fmaf(pc.whi, gv[2], pc.wlo * gv[3]);
+                    o.w = fmaf(pc.whi, gv[3], pc.wlo * gv[4]);
+                    store_f32x4<true>(orow + c, o);
+                }
+                if constexpr (GOFF) {
+                    const float4 sv = *(const float4 *)(srow + c);   // 16-byte aligned
+                    part += (double)sv.x * ((double)gv[1] - (double)gv[0]);
+                    part += (double)sv.y * ((double)gv[2] - (double)gv[1]);
+                    part += (double)sv.z * ((double)gv[3] - (double)gv[2]);
+                    part += (double)sv.w * ((double)gv[4] - (double)gv[3]);
+                }
+            }
+        } else {
+            for (int64_t c = threadIdx.x; c < C; c += BLOCK) {
+                const int64_t x = c + pc.k;
+                const float g0 = load_px(grow, x, W);
+                const float g1 = load_px(grow, x + 1, W);
+                if constexpr (GIN) orow[c] = fmaf(pc.whi, g0, pc.wlo * g1);
+                if constexpr (GOFF) part += (double)srow[c] * ((double)g1 - (double)g0);
+            }
         }
     }
     if constexpr (GOFF) {

@@ -30,11 +30,12 @@ def _dev(a, dtype=None):
     return t.to(DEV, dtype=dtype) if dtype is not None else t.to(DEV)
 
 
+@pytest.mark.parametrize("c", [301, 300])          # 300: four columns per thread
 @pytest.mark.parametrize("kind", ["frac", "neg", "int", "jitter"])
-def test_adjoint_and_shear_grad_match_oracle(kind):
-    _say(f"backward parity: {kind}")
+def test_adjoint_and_shear_grad_match_oracle(kind, c):
+    _say(f"backward parity: {kind}, {c} columns")
     rng = np.random.default_rng(3)
-    n, r, c = 23, 17, 301
+    n, r = 23, 17
     s = synth.blob_stack((n, r, c), 40, 5, dtype="f32").numpy()
     if kind == "frac":
         off = oracle.offsets_uniform(n, 2.6458)
