@@ -73,11 +73,21 @@ extern "C" int dsk_rolling_update_u16(const uint16_t *plane, int32_t n, dsk_dims
     const int st = check_frame(d, origin, out_width);
     if (st != DSK_OK) return st;
     const int64_t rw = (int64_t)d.rows * out_width;
-    const int64_t blocks = (rw + 255) / 256;
-    if (blocks > kMaxI32) return DSK_ESHAPE;
     RollArgs a{plane, vol, tree, sum64, psum, pmax, offsets_dev, shift_px, (double)origin,
                out_width, d.planes, d.rows, d.cols, n, levels};
-    hipLaunchKernelGGL(k_rolling_update<uint16_t>, dim3((unsigned)blocks), dim3(256), 0, stream,
-                       a);
+    // 4 pixels per thread when every array is 16-byte aligned and the
+    // plane's pixel count is a multiple of 4
+    const bool vec = rw % 4 == 0 && ((uintptr_t)vol & 15) == 0 && ((uintptr_t)sum64 & 15) == 0 &&
+                     ((uintptr_t)psum & 15) == 0 && ((uintptr_t)pmax & 15) == 0 &&
+                     (levels == 0 || ((uintptr_t)tree & 15) == 0);
+    const int64_t per = vec ? 4 : 1;
+    const int64_t blocks = (rw / per + 255) / 256;
+    if (blocks > kMaxI32) return DSK_ESHAPE;
+    if (vec)
+        hipLaunchKernelGGL(k_rolling_update4<uint16_t>, dim3((unsigned)blocks), dim3(256), 0,
+                           stream, a);
+    else
+        hipLaunchKernelGGL(k_rolling_update<uint16_t>, dim3((unsigned)blocks), dim3(256), 0,
+                           stream, a);
     return hip_status(hipGetLastError());
 }

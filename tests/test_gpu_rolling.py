@@ -18,10 +18,12 @@ def _fwd(stack, shift):
     return dsk.deskew(stack, offsets=np.arange(n) * shift)
 
 
-def test_in_order_equals_forward_bitwise():
-    st = synth.blob_stack((64, 128, 256), 50, 0).to(DEV)
-    rv = RollingView(64, 128, 256, 30.0, 0.4, 0.115)
-    for n in range(64):
+@pytest.mark.parametrize("shape", [(64, 128, 256), (13, 7, 61)])   # 7 x W odd: one pixel per thread
+def test_in_order_equals_forward_bitwise(shape):
+    n_img = shape[0]
+    st = synth.blob_stack(shape, 50, 0).to(DEV)
+    rv = RollingView(*shape, 30.0, 0.4, 0.115)
+    for n in range(n_img):
         rv.update(n, st[n])
     ref = dsk.deskew(st, 30.0, 0.4, 0.115)
     torch.cuda.synchronize()
