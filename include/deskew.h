@@ -75,9 +75,10 @@ typedef struct {
  * as fit); pace_gbs: plane pacing of the vector kernel -- a wavefront that
  * runs ahead of the schedule "the launch's resident wavefronts move this
  * many GB/s" sleeps briefly, which keeps the wavefronts on neighbouring
- * planes and the write stream local (0 = no pacing; launches without a
- * volume are not paced; pacing only delays, it never waits on another
- * wavefront).  Every shape gives bitwise identical results. */
+ * planes and the write stream local; without a volume, wavefronts whose
+ * planes start late wait for their turn (0 = no pacing; pacing only
+ * delays, it never waits on another wavefront).  Every shape gives bitwise
+ * identical results. */
 typedef struct {
     int32_t block, per_thread, nt_store, unroll, wg_per_cu, pace_gbs;
 } dsk_tune;
@@ -148,7 +149,8 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
 
 /* Launch-shape tuner for one frame (the shape a live stream deskews over
  * and over).  Times candidate shapes -- one or two 4-column groups per
- * lane, unpaced and paced at 5000-6000 GB/s, and the default -- for `reps`
+ * lane, unpaced and paced at 5000-6000 GB/s with a volume (9000-12000
+ * without), and the default -- for `reps`
  * rounds (3..64), a burst of 3 back-to-back launches of each shape per
  * round, round-robin after one untimed round, on the caller's own buffers
  * and stream, and returns in *tune, among the shapes whose mean time per

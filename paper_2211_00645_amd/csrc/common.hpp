@@ -25,9 +25,13 @@ constexpr int64_t kMaxI32 = 2147483647;
 constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5800};
 
 // Default shape of launches without a volume (projections only, the live
-// view): they only read and are not paced; a 4-plane load-ahead keeps
-// enough reads in flight (on the 512x512x2048 stack 0.233 ms against 0.25
-// for 2 planes).
+// view): a 4-plane load-ahead keeps enough reads in flight (on the
+// 512x512x2048 stack 0.228 ms against 0.240 for 2 planes).  They only
+// read, and are not paced by default: a pace above what the device reaches
+// only makes the wavefronts whose planes start late wait for their turn
+// instead of competing with the others at the start, which gained 1-5% on
+// that stack (9000-11000 GB/s) and lost 1-3% on wider frames (more tiles
+// than resident wavefronts); dsk_deskew_autotune tries both.
 constexpr dsk_tune kDefaultProjTune = {64, 4, 1, 4, 0, 0};
 
 inline const dsk_tune &default_tune(const void *vol) {

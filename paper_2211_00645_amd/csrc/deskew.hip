@@ -80,12 +80,12 @@ int device_cus() {
 
 // Workgroups of the vector kernel one compute unit holds at once (cached
 // per kernel instance).
-template <typename TIn, int B, int G, int U, bool NT>
+template <typename TIn, int B, int G, int U, bool NT, bool VOL>
 static int vec_resident_per_cu() {
     static int occ = 0;
     if (occ <= 0) {
         int o = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_forward_vec<TIn, B, G, U, NT, true>, B,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, k_forward_vec<TIn, B, G, U, NT, VOL>, B,
                                                          0) != hipSuccess ||
             o <= 0)
             o = 1;
@@ -104,17 +104,20 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
             auto kern = a.vol ? k_forward_vec<TIn, B, PT / 4, U, NT, true>
                               : k_forward_vec<TIn, B, PT / 4, U, false, false>;
             const int64_t blocks = tiles * a.R + edge;
-            if (pace_gbs > 0 && a.vol) {
-                // pacing keeps the volume's write stream local; a launch
-                // without a volume only reads and is not paced.  One
-                // workgroup's share of a plane's bytes, timed at pace_gbs
+            // Pacing holds every wavefront to one plane schedule: with a
+            // volume it keeps the write stream local; without one, wavefronts
+            // whose plane ranges start late wait for their turn.
+            if (pace_gbs > 0) {
+                // one workgroup's share of a plane's bytes, timed at pace_gbs
                 const double plane_bytes = (double)a.R * a.C * sizeof(TIn) +
                                            (a.vol ? 4.0 * (double)a.R * (double)a.W : 0.0);
                 const double t = plane_bytes / (double)blocks / ((double)pace_gbs * 1e9) * 1e8 *
                                  65536.0;
                 a.tau_wg = t >= 4.0e9 ? 4000000000u : (uint32_t)t;
                 const int64_t cap =
-                    (int64_t)vec_resident_per_cu<TIn, B, PT / 4, U, NT>() * device_cus();
+                    (int64_t)(a.vol ? vec_resident_per_cu<TIn, B, PT / 4, U, NT, true>()
+                                    : vec_resident_per_cu<TIn, B, PT / 4, U, false, false>()) *
+                    device_cus();
                 a.pace_cap = (int32_t)(cap < 1 ? 1 : (cap > kMaxI32 ? kMaxI32 : cap));
             }
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), block, 0, s, a, (int)tiles);

@@ -322,9 +322,13 @@ __device__ __forceinline__ int edge_col(const RowGeo &g, int W, int j) {
 }
 
 // One vector tile: row r, whole groups [tile*BLOCK*G, (tile+1)*BLOCK*G) of
-// the row.  Thread t owns groups tile*BLOCK*G + t + BLOCK*g, clamped to the
-// row's last group, so every lane writes whole 16-byte groups (lanes past
-// the end repeat the last group: identical values to identical addresses).
+// the row.  With a volume, thread t owns groups tile*BLOCK*G + t + BLOCK*g
+// (a wavefront's stores of one group index are contiguous); without one, a
+// lane's G groups sit side by side (wavefront w, lane l: groups
+// tile*BLOCK*G + 64 G w + G l + g), so a wavefront reads one contiguous run
+// of 256 G columns per plane.  Group indices are clamped to the row's last
+// group, so every lane writes whole 16-byte groups (lanes past the end
+// repeat the last group: identical values to identical addresses).
 //
 // Per-plane values come 64 planes at a time (a chunk): lane l of every
 // wavefront computes plane (c0 + l)'s coefficients and window offset, and
@@ -341,13 +345,16 @@ __device__ __forceinline__ int edge_col(const RowGeo &g, int W, int j) {
 //
 // Without a volume the pass only reads, and a pipeline that drains at every
 // chunk or class boundary leaves the memory system idle each time all
-// wavefronts drain together.  So the tile first finds, per group, the range
-// of planes that touch its columns, then runs one software-pipelined loop
-// over that range: loads go out U planes ahead across chunk boundaries (the
-// next chunk's values computed in advance), always with clamped addresses,
-// and a group of U planes is masked unless all of them are IN.  Planes at
-// the unaligned ends of the range, and planes whose rows lie at a stack end,
-// go one at a time through the exact-bounds path.
+// wavefronts drain together.  So the wavefront first finds the range of
+// planes that touch any of its columns, then runs one software-pipelined
+// loop over that range, all of its groups per plane: loads go out U planes
+// ahead across chunk boundaries (the next chunk's values computed in
+// advance), always with clamped addresses, and U planes are masked unless
+// all of them are IN for every group.  Planes at the unaligned ends of the
+// range, and planes whose rows lie at a stack end, go one at a time through
+// the exact-bounds path.  A plane's window of a wavefront spans 256 G
+// columns plus one: 4 G + 1 cache lines where 4 G carry its share, so wider
+// lanes (G = 2) fetch fewer lines twice.
 //
 // Every path does the same per-voxel arithmetic and adds planes to the FP64
 // sum in plane order, so no class or pass split changes a bit of the result.
@@ -369,7 +376,7 @@ struct VecTile {
     bool alive;
     uint64_t t0;                       // pacing origin (this wavefront's start)
     uint32_t tau;                      // pacing period per plane, 1/256 ticks (0 = none)
-    uint32_t taug;                     // the same per plane and group
+    uint32_t taug;                     // per step of the wavefront's walk
     double acc[G][4];
     float mx[G][4];
     // chunk lane data (plane c0 + lane): first needed pixel of group 0 (s0),
@@ -387,7 +394,7 @@ struct VecTile {
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
         lane = (int)threadIdx.x & 63;
         const int base = tile * BLOCK * G;
-        alive = base + 64 * wv < ng;
+        alive = base + (VOL ? 64 : 64 * G) * wv < ng;
         // the plane pitch is a multiple of 4, so every plane's row start has
         // this residue
         constexpr int K = Win::kAlign;
@@ -401,22 +408,30 @@ struct VecTile {
         last_special = ((int64_t)(N - 1) * rstep + g0 + C + 8 > a.in_hi) ? N - 1 : -1;
         rp0 = a.in + (int64_t)r * a.in_row;
         op0 = VOL ? a.vol + (int64_t)r * W : nullptr;
-        tau = VOL ? a.tau256 : 0;
-        if (VOL && a.pace_cap > 0) {
+        tau = a.tau256;
+        if (a.pace_cap > 0) {
             const int64_t cap = a.pace_cap, batch = (int64_t)blockIdx.x / cap;
             const int64_t left = (int64_t)gridDim.x - batch * cap;
             const uint64_t t = ((uint64_t)a.tau_wg * (uint64_t)(left < cap ? left : cap)) >> 8;
             tau = t > 4000000000ull ? 4000000000u : (uint32_t)t;
         }
-        // a wavefront covers its G groups one after another, chunk by chunk
-        taug = tau / G;
+        // with a volume a wavefront covers its G groups one after another,
+        // chunk by chunk; without one, all of them per plane
+        taug = VOL ? tau / G : tau;
         t0 = tau ? pace_clock() : 0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int w0 = base + 64 * wv + BLOCK * g;
-            gi[g] = min(base + (int)threadIdx.x + BLOCK * g, ng - 1);
-            gfirst[g] = min(w0, ng - 1);
-            glast[g] = min(w0 + 63, ng - 1);
+            if constexpr (VOL) {
+                const int w0 = base + 64 * wv + BLOCK * g;
+                gi[g] = min(base + (int)threadIdx.x + BLOCK * g, ng - 1);
+                gfirst[g] = min(w0, ng - 1);
+                glast[g] = min(w0 + 63, ng - 1);
+            } else {
+                const int w0 = base + 64 * G * wv + g;
+                gi[g] = min(w0 + G * lane, ng - 1);
+                gfirst[g] = min(w0, ng - 1);
+                glast[g] = min(w0 + G * 63, ng - 1);
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 acc[g][i] = 0.0;
@@ -436,8 +451,16 @@ struct VecTile {
 
     // Positions [s0 + 4 gfirst, s0 + 4 glast + 5) of the wavefront's group g.
     __device__ __forceinline__ int cls_of(int s0, int g) const {
-        const int q0 = s0 + 4 * gfirst[g];
-        const int q1 = s0 + 4 * glast[g] + 5;
+        return cls_range(s0 + 4 * gfirst[g], s0 + 4 * glast[g] + 5);
+    }
+
+    // All the wavefront's positions (groups side by side: group 0 holds the
+    // lowest column, group G - 1 the highest).
+    __device__ __forceinline__ int cls_span(int s0) const {
+        return cls_range(s0 + 4 * gfirst[0], s0 + 4 * glast[G - 1] + 5);
+    }
+
+    __device__ __forceinline__ int cls_range(int q0, int q1) const {
         if (q0 >= 0 && q1 <= C) return IN;
         if (q1 <= 0 || q0 >= C) return OUT;
         return MIXED;
@@ -652,18 +675,18 @@ struct VecTile {
 
     // ---- projections only ------------------------------------------------
 
-    // Lane values of the chunk at c0 and the wavefront's IN / OUT ballots for
-    // group g (bits of planes past the stack end clear).
+    // Lane values of the chunk at c0 and the wavefront's IN / OUT ballots over
+    // all its groups (bits of planes past the stack end clear).
     struct Chunk {
         int c0, win;
         float wlo, whi;
         uint64_t bin, bout;
     };
 
-    __device__ __forceinline__ void load_chunk(int g, int c0, Chunk &k) {
+    __device__ __forceinline__ void load_chunk(int c0, Chunk &k) {
         chunk(c0);
         const int cn = min(64, N - c0);
-        const int cl = cls_of(ls0, g);
+        const int cl = cls_span(ls0);
         k.c0 = c0;
         k.win = lwin;
         k.wlo = lwlo;
@@ -672,22 +695,26 @@ struct VecTile {
         k.bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
     }
 
-    // Planes [n0, n1) of group g one at a time (ascending), each with its
-    // chunk's values (k holds the chunk last loaded).
-    __device__ __forceinline__ void singles(int g, int n0, int n1, Chunk &k) {
+    // Planes [n0, n1) one at a time (ascending), every group, each plane with
+    // its chunk's values (k holds the chunk last loaded).
+    __device__ __forceinline__ void singles(int n0, int n1, Chunk &k) {
         for (int n = n0; n < n1; ++n) {
-            if (n < k.c0 || n >= k.c0 + 64) load_chunk(g, n & ~63, k);
-            float d[4];
-            single(g, n, n - k.c0, k.win, k.wlo, k.whi, d);
+            if (n < k.c0 || n >= k.c0 + 64) load_chunk(n & ~63, k);
+            pace_until(t0, taug, n);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                float d[4];
+                single(g, n, n - k.c0, k.win, k.wlo, k.whi, d);
+            }
         }
     }
 
     // Issue the window loads of planes n .. n + U - 1 (or U times plane n
-    // with rep set), each taking its values from the chunk it lies in: cur
-    // or the next one.
+    // with rep set), every group, each plane taking its values from the
+    // chunk it lies in: cur or the next one.
     template <int U>
-    __device__ __forceinline__ void issue_group(int g, int n, bool rep, const Chunk &cur,
-                                                const Chunk &nxt, Win w[U], int v[U]) const {
+    __device__ __forceinline__ void issue_planes(int n, bool rep, const Chunk &cur,
+                                                 const Chunk &nxt, Win w[U][G], int v[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = rep ? n : n + u;
@@ -695,101 +722,124 @@ struct VecTile {
             const int vv = __builtin_amdgcn_readlane(in_nxt ? nxt.win : cur.win,
                                                      p - (in_nxt ? nxt.c0 : cur.c0));
             v[u] = vv;
-            fetch<true>(g, rp0 + (int64_t)p * rstep, vv, w[u]);
+#pragma unroll
+            for (int g = 0; g < G; ++g) fetch<true>(g, rp0 + (int64_t)p * rstep, vv, w[u][g]);
         }
+    }
+
+    template <int U>
+    __device__ __forceinline__ static void settle_planes(const Win w[U][G]) {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int g = 0; g < G; ++g) w[u][g].settle();
     }
 
     // Interpolate and accumulate planes n .. n + U - 1 (all in chunk cur),
     // masked unless all of them are IN.
     template <int U>
-    __device__ __forceinline__ void compute_group(int g, int n, const Chunk &cur, const Win w[U],
-                                                  const int v[U]) {
+    __device__ __forceinline__ void compute_planes(int n, const Chunk &cur, const Win w[U][G],
+                                                   const int v[U]) {
         const int li = n - cur.c0;
         const uint64_t full = (U == 64) ? ~0ull : ((1ull << U) - 1);
         float d[4];
         if (((cur.bin >> li) & full) == full) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                compute<false>(g, w[u], v[u], lane_f(cur.wlo, li + u), lane_f(cur.whi, li + u), d);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    compute<false>(g, w[u][g], v[u], lane_f(cur.wlo, li + u),
+                                   lane_f(cur.whi, li + u), d);
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                compute<true>(g, w[u], v[u], lane_f(cur.wlo, li + u), lane_f(cur.whi, li + u), d);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    compute<true>(g, w[u][g], v[u], lane_f(cur.wlo, li + u),
+                                  lane_f(cur.whi, li + u), d);
         }
     }
 
     __device__ __forceinline__ void run_projections() {
         constexpr int U = UNR;
+        // planes that touch any of the wavefront's columns: [n_lo, n_hi);
+        // per group, whether some plane misses all of its columns
+        int n_lo = N, n_hi = 0;
+        bool any_out[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) any_out[g] = false;
+        Chunk k;
+        for (int c0 = 0; c0 < N; c0 += 64) {
+            load_chunk(c0, k);
+            const int cn = min(64, N - c0);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                any_out[g] = any_out[g] ||
+                             __builtin_amdgcn_ballot_w64(lane < cn && cls_of(ls0, g) == OUT) != 0;
+            const uint64_t valid = cn == 64 ? ~0ull : ((1ull << cn) - 1);
+            const uint64_t act = valid & ~k.bout;
+            if (act) {
+                n_lo = min(n_lo, c0 + (int)__builtin_ctzll(act));
+                n_hi = max(n_hi, c0 + 64 - (int)__builtin_clzll(act));
+            }
+        }
+        // a plane that misses all of a group's columns is zero at each of
+        // them (inside the range such planes also come out zero, masked)
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            // planes that touch the group's columns: [n_lo, n_hi)
-            int n_lo = N, n_hi = 0;
-            bool any_out = false;
-            Chunk k;
-            for (int c0 = 0; c0 < N; c0 += 64) {
-                load_chunk(g, c0, k);
-                const int cn = min(64, N - c0);
-                const uint64_t valid = cn == 64 ? ~0ull : ((1ull << cn) - 1);
-                const uint64_t act = valid & ~k.bout;
-                any_out = any_out || k.bout != 0;
-                if (act) {
-                    n_lo = min(n_lo, c0 + (int)__builtin_ctzll(act));
-                    n_hi = max(n_hi, c0 + 64 - (int)__builtin_clzll(act));
-                }
-            }
-            // an all-OUT plane is zero at every column of the group
-            if (any_out) {
+            if (any_out[g]) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
             }
-            if (n_lo >= n_hi) continue;
-            // the pipelined range: whole groups of U planes, aligned (so a
-            // group never spans two chunks), rows at a stack end excluded
-            const int lo = n_lo + ((first_special == 0 && n_lo == 0) ? 1 : 0);
-            const int hi = n_hi - ((last_special == N - 1 && n_hi == N) ? 1 : 0);
-            int mlo = (lo + U - 1) / U * U, mhi = hi / U * U;
-            if (mlo >= mhi) mlo = mhi = n_hi;
-            singles(g, n_lo, mlo, k);
-            if (mlo < mhi) {
-                Chunk cur, nxt;
-                load_chunk(g, mlo & ~63, cur);
-                nxt = cur;
-                if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
-                Win A[U], B[U];
-                int va[U], vb[U];
-                issue_group<U>(g, mlo, false, cur, nxt, A, va);
-#pragma unroll
-                for (int u = 0; u < U; ++u) A[u].settle();
-                int n = mlo;
-                // two groups per trip, alternating the window registers
-                while (true) {
-                    bool rep = n + U >= mhi;
-                    issue_group<U>(g, rep ? mhi - 1 : n + U, rep, cur, nxt, B, vb);
-                    compute_group<U>(g, n, cur, A, va);
-#pragma unroll
-                    for (int u = 0; u < U; ++u) B[u].settle();
-                    n += U;
-                    if (n >= mhi) break;
-                    if (n >= cur.c0 + 64) {
-                        cur = nxt;
-                        if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
-                    }
-                    rep = n + U >= mhi;
-                    issue_group<U>(g, rep ? mhi - 1 : n + U, rep, cur, nxt, A, va);
-                    compute_group<U>(g, n, cur, B, vb);
-#pragma unroll
-                    for (int u = 0; u < U; ++u) A[u].settle();
-                    n += U;
-                    if (n >= mhi) break;
-                    if (n >= cur.c0 + 64) {
-                        cur = nxt;
-                        if (cur.c0 + 64 < N) load_chunk(g, cur.c0 + 64, nxt);
-                    }
-                }
-                k = cur;
-            }
-            singles(g, mhi, n_hi, k);
         }
+        if (n_lo >= n_hi) return;
+        // the pipelined range: whole steps of U planes, aligned (so a step
+        // never spans two chunks), rows at a stack end excluded
+        const int lo = n_lo + ((first_special == 0 && n_lo == 0) ? 1 : 0);
+        const int hi = n_hi - ((last_special == N - 1 && n_hi == N) ? 1 : 0);
+        int mlo = (lo + U - 1) / U * U, mhi = hi / U * U;
+        if (mlo >= mhi) mlo = mhi = n_hi;
+        singles(n_lo, mlo, k);
+        if (mlo < mhi) {
+            Chunk cur, nxt;
+            load_chunk(mlo & ~63, cur);
+            nxt = cur;
+            if (cur.c0 + 64 < N) load_chunk(cur.c0 + 64, nxt);
+            Win A[U][G], B[U][G];
+            int va[U], vb[U];
+            pace_until(t0, taug, mlo);
+            issue_planes<U>(mlo, false, cur, nxt, A, va);
+            settle_planes<U>(A);
+            int n = mlo;
+            // two steps per trip, alternating the window registers; a paced
+            // wavefront sleeps with the next loads in flight
+            while (true) {
+                bool rep = n + U >= mhi;
+                issue_planes<U>(rep ? mhi - 1 : n + U, rep, cur, nxt, B, vb);
+                pace_until(t0, taug, n + U);
+                compute_planes<U>(n, cur, A, va);
+                settle_planes<U>(B);
+                n += U;
+                if (n >= mhi) break;
+                if (n >= cur.c0 + 64) {
+                    cur = nxt;
+                    if (cur.c0 + 64 < N) load_chunk(cur.c0 + 64, nxt);
+                }
+                rep = n + U >= mhi;
+                issue_planes<U>(rep ? mhi - 1 : n + U, rep, cur, nxt, A, va);
+                pace_until(t0, taug, n + U);
+                compute_planes<U>(n, cur, B, vb);
+                settle_planes<U>(A);
+                n += U;
+                if (n >= mhi) break;
+                if (n >= cur.c0 + 64) {
+                    cur = nxt;
+                    if (cur.c0 + 64 < N) load_chunk(cur.c0 + 64, nxt);
+                }
+            }
+            k = cur;
+        }
+        singles(mhi, n_hi, k);
     }
 
     __device__ __forceinline__ void run() {
@@ -921,16 +971,21 @@ __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x
 // One group per lane with a shallow plane pipeline (UNR <= 2) writing the
 // volume is built for 8 wavefronts per SIMD, so that a 512-row stack's tiles
 // are all resident at once (plane pacing then holds every wavefront of the
-// launch to one schedule).  Launches without a volume are not paced; with
-// one group per lane they are built for 7 wavefronts per SIMD (72
-// registers, room for a 4-plane pipeline), so the 512-row stack's 7168
-// tiles are again all resident at once; with two groups for 6.
-constexpr int vec_waves_per_eu(int g, int unr, bool vol) {
-    return vol ? (g == 1 && unr <= 2 ? 8 : 1) : (g == 1 ? 7 : 6);
+// launch to one schedule).  Launches without a volume get the most
+// wavefronts that leave room for their registers: about 36 besides the
+// G groups' sums and maxima (12 each) and 2 U G plane windows (3 registers
+// for 16-bit input, 5 for 32-bit), out of 512 per lane.  A 4-plane
+// pipeline of 16-bit windows, one group per lane, fits 7 (72 registers),
+// so the 512-row stack's 7168 tiles are again all resident at once.
+constexpr int vec_waves_per_eu(int g, int unr, bool vol, int in_bytes) {
+    if (vol) return g == 1 && unr <= 2 ? 8 : 1;
+    const int need = 36 + 12 * g + 2 * unr * g * (in_bytes > 2 ? 5 : 3);
+    const int w = 512 / ((need + 7) / 8 * 8);
+    return w > 8 ? 8 : (w < 1 ? 1 : w);
 }
 
 template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
-__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR, VOL)) void k_forward_vec(
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR, VOL, (int)sizeof(TIn))) void k_forward_vec(
     FwdArgs<TIn> a, int tiles_x) {
     fwd_vec_block<TIn, BLOCK, G, UNR, NT, VOL>(
         a, tiles_x, VOL ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
@@ -954,7 +1009,7 @@ struct JobDev {
 // for that job, so outputs are bitwise equal.  One launch covers jobs that
 // all write a volume (VOL) or all do not.
 template <int BLOCK, int PT, int UNR, bool NT, bool VOL>
-__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL)) void k_forward_jobs(
+__global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL, 2)) void k_forward_jobs(
     const JobDev *__restrict__ jobs, int n_jobs, int64_t total_tiles) {
     const int64_t grid = gridDim.x;
     const int64_t me = blockIdx.x;

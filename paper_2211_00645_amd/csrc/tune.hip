@@ -120,10 +120,13 @@ namespace {
 // Without a volume nothing is paced: groups and pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
     if (!paced) {
-        std::vector<dsk_tune> c{kDefaultProjTune};
-        for (int pt : {4, 8})
-            for (int u : {2, 4})
-                if (pt != 4 || u != 4) c.push_back(dsk_tune{64, pt, 1, u, 0, 0});
+        // without a volume: the default (unpaced), its shape at 9000 and
+        // 12000, a 2-plane pipeline unpaced and at 9000, two groups per
+        // lane unpaced
+        std::vector<dsk_tune> c{kDefaultProjTune, dsk_tune{64, 4, 1, 4, 0, 9000},
+                                dsk_tune{64, 4, 1, 4, 0, 12000}, dsk_tune{64, 4, 1, 2, 0, 0},
+                                dsk_tune{64, 4, 1, 2, 0, 9000}};
+        for (int u : {2, 4}) c.push_back(dsk_tune{64, 8, 1, u, 0, 0});
         return c;
     }
     std::vector<dsk_tune> c{kDefaultTune};
@@ -322,7 +325,8 @@ extern "C" int dsk_deskew_autotune(const void *in, int in_is_f32, dsk_dims d,
         const size_t bi = choose(front, fscore);
         best = front[bi];
         best_ms = fscore[bi];
-        const size_t di = step_down(cand, best);
+        // a pace stays clear of its cliff only where wavefronts write
+        const size_t di = vol ? step_down(cand, best) : cand.size();
         if (di < cand.size()) {
             best = cand[di];
             best_ms = score[di];

@@ -16,7 +16,7 @@ from paper_2211_00645_amd import synth
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-PACES = {0, 5000, 5200, 5400, 5500, 5600, 5700, 5800, 5900, 6000}
+PACES = {0, 5000, 5200, 5400, 5500, 5600, 5700, 5800, 5900, 6000, 9000, 12000}
 
 
 def _say(msg):
@@ -53,12 +53,13 @@ def test_tuned_shape_gives_the_default_result(shape, angle, step):
 
 
 def test_projections_only_tuner():
-    """A frame tuned without a volume gets one of the unpaced candidates,
-    and its projections are bitwise the default shape's."""
+    """A frame tuned without a volume gets one of its own candidates
+    (unpaced, or paced above what any device reaches), and its projections
+    are bitwise the default shape's."""
     shape = (130, 18, 333)
     st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 6, device=DEV)
     got = dsk.autotune(st, 35.0, 0.4, 0.115, vol=False, reps=3)
-    assert _valid(got["tune"]) and got["tune"]["pace_gbs"] == 0
+    assert _valid(got["tune"]) and got["tune"]["pace_gbs"] in (0, 9000, 12000)
     ref = dsk.deskew(st, 35.0, 0.4, 0.115, vol=False)
     res = dsk.deskew(st, 35.0, 0.4, 0.115, vol=False, tune=got["tune"])
     torch.cuda.synchronize()
