@@ -711,19 +711,30 @@ struct VecTile {
 
     // Issue the window loads of planes n .. n + U - 1 (or U times plane n
     // with rep set), every group, each plane taking its values from the
-    // chunk it lies in: cur or the next one.
+    // chunk it lies in: cur or the next one.  n is a multiple of U (or rep),
+    // so the planes lie in one chunk; when all of them are IN the addresses
+    // need no clamping.
     template <int U>
     __device__ __forceinline__ void issue_planes(int n, bool rep, const Chunk &cur,
                                                  const Chunk &nxt, Win w[U][G], int v[U]) const {
+        const Chunk &ch = n >= cur.c0 + 64 ? nxt : cur;
+        const uint64_t full = rep ? 1ull : ((U == 64) ? ~0ull : ((1ull << U) - 1));
+        if (((ch.bin >> (n - ch.c0)) & full) == full)
+            issue_planes_as<U, false>(n, rep, ch, w, v);
+        else
+            issue_planes_as<U, true>(n, rep, ch, w, v);
+    }
+
+    template <int U, bool MASK>
+    __device__ __forceinline__ void issue_planes_as(int n, bool rep, const Chunk &ch, Win w[U][G],
+                                                    int v[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int p = rep ? n : n + u;
-            const bool in_nxt = p >= cur.c0 + 64;
-            const int vv = __builtin_amdgcn_readlane(in_nxt ? nxt.win : cur.win,
-                                                     p - (in_nxt ? nxt.c0 : cur.c0));
+            const int vv = __builtin_amdgcn_readlane(ch.win, p - ch.c0);
             v[u] = vv;
 #pragma unroll
-            for (int g = 0; g < G; ++g) fetch<true>(g, rp0 + (int64_t)p * rstep, vv, w[u][g]);
+            for (int g = 0; g < G; ++g) fetch<MASK>(g, rp0 + (int64_t)p * rstep, vv, w[u][g]);
         }
     }
 

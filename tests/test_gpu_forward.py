@@ -162,6 +162,14 @@ RAGGED = [
 ]
 
 
+# projections-only shapes beside the default: two groups per lane side by
+# side (one walk over the union of their plane ranges), paced, and a
+# 256-thread workgroup
+PROJ_TUNES = [dict(block=64, per_thread=8, nt_store=1, unroll=2),
+              dict(block=256, per_thread=8, nt_store=1, unroll=4, pace_gbs=9000),
+              dict(block=64, per_thread=4, nt_store=1, unroll=4, pace_gbs=9000)]
+
+
 def _offsets(kind, n, seed):
     rng = np.random.default_rng(seed)
     if kind == "frac":
@@ -199,6 +207,10 @@ def test_ragged_shapes(n, r, c, kind, seed, dtype):
     assert (out["origin"], out["width"]) == (ref["origin"], ref["width"])
     for k in ("psum", "pmax"):
         assert torch.equal(proj[k], out[k]), f"projections-only {k}"
+    for t in PROJ_TUNES:
+        p2 = dsk.deskew(st.to(DEV), offsets=off, vol=False, tune=t)
+        for k in ("psum", "pmax"):
+            assert torch.equal(p2[k], out[k]), (t, k)
     v = _to_np(out["vol"])
     if kind in ("int", "zero"):
         assert v.tobytes() == ref["vol"].tobytes()
@@ -286,11 +298,12 @@ def test_signed_stack_maximum(step):
     st = -1.0 - synth.blob_stack((n, r, c), 8, 14, dtype="f32")
     off = oracle.offsets_uniform(n, oracle.shift_px(35.0, step, 0.115))
     ref = oracle.deskew(st.numpy(), off)
-    for vol in (True, False):
-        out = dsk.deskew(st.to(DEV), offsets=off, vol=vol)
+    for vol, tune in ((True, None), (False, None), (False, PROJ_TUNES[0])):
+        out = dsk.deskew(st.to(DEV), offsets=off, vol=vol, tune=tune)
         torch.cuda.synchronize()
         pm = _to_np(out["pmax"])
-        _check_close(pm, ref["pmax"], np.abs(ref["pmax"]).astype(np.float64), f"pmax vol={vol}")
+        _check_close(pm, ref["pmax"], np.abs(ref["pmax"]).astype(np.float64),
+                     f"pmax vol={vol} tune={tune}")
         if step == 0.0:
             assert (pm < 0).all()
 
