@@ -574,31 +574,34 @@ struct VecTile {
         store_f32x4<NT>(orow + xcol(g), f32x4{d[0], d[1], d[2], d[3]});
     }
 
-    // Chunk planes [0, cn) for group g, software-pipelined: the loads of the
-    // next U planes go out before the current U planes are interpolated and
-    // stored, and are waited for after those stores.  Each plane issues
-    // exactly one 16-byte store per lane with no branch around it, so the
-    // compiler counts the stores and the wait for the loads leaves them in
-    // flight: stores never hold up the plane loop.
+    // Chunk planes [l0, l1) of a chunk of cn planes for group g,
+    // software-pipelined: the loads of the next U planes go out before the
+    // current U planes are interpolated and stored, and are waited for after
+    // those stores.  Each plane issues exactly one 16-byte store per lane
+    // with no branch around it, so the compiler counts the stores and the
+    // wait for the loads leaves them in flight: stores never hold up the
+    // plane loop.
     template <int U, bool MASK>
-    __device__ __forceinline__ void pipe_loop(int g, int c0, int cn, const TIn *rpc, float *op) {
-        const int groups = cn / U;
-        float *orow = op;
-        int li = 0;
+    __device__ __forceinline__ void pipe_loop(int g, int c0, int cn, int l0, int l1,
+                                              const TIn *rpc, float *op) {
+        const int groups = (l1 - l0) / U;
+        float *orow = op + (int64_t)l0 * ostep;
+        int li = l0;
         if (groups > 0) {
             Win cur[U];
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                fetch<MASK>(g, rpc + (int64_t)u * rstep, __builtin_amdgcn_readlane(lwin, u), cur[u]);
+                fetch<MASK>(g, rpc + (int64_t)(l0 + u) * rstep,
+                            __builtin_amdgcn_readlane(lwin, l0 + u), cur[u]);
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u].settle();
             for (int k = 0; k < groups; ++k) {
-                // the next U planes (past the chunk's end: its last plane,
+                // the next U planes (past the range's end: its last plane,
                 // in bounds, never used)
                 Win nxt[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const int ln = min(li + U + u, cn - 1);
+                    const int ln = min(li + U + u, l1 - 1);
                     fetch<MASK>(g, rpc + (int64_t)ln * rstep, __builtin_amdgcn_readlane(lwin, ln),
                                 nxt[u]);
                 }
@@ -620,7 +623,7 @@ struct VecTile {
                 li += U;
             }
         }
-        for (; li < cn; ++li) {
+        for (; li < l1; ++li) {
             Win one;
             fetch<MASK>(g, rpc + (int64_t)li * rstep, __builtin_amdgcn_readlane(lwin, li), one);
             float d[4];
@@ -631,44 +634,55 @@ struct VecTile {
         }
     }
 
+    // A plane whose row lies at a stack end (the chunk's plane li) through
+    // the exact-bounds path.
+    __device__ __forceinline__ void special_plane(int g, int c0, int li, float *op) {
+        float d[4];
+        single(g, c0 + li, li, lwin, lwlo, lwhi, d);
+        store(g, op + (int64_t)li * ostep, d);
+    }
+
     __device__ __forceinline__ void run_volume() {
         for (int c0 = 0; c0 < N; c0 += 64) {
             const int cn = min(64, N - c0);
             chunk(c0);
-            const bool special = (first_special >= c0 && first_special < c0 + cn) ||
-                                 (last_special >= c0 && last_special < c0 + cn);
+            // only plane 0 and plane N - 1 can be special, and only the
+            // special plane itself leaves the chunk's loop: the others,
+            // [l0, l1), run as in any chunk (a special chunk's planes at the
+            // end of a launch, one at a time, held every other wavefront up)
+            const bool sp_first = first_special == c0;
+            const bool sp_last = last_special == c0 + cn - 1 && !(sp_first && cn == 1);
+            const int l0 = sp_first ? 1 : 0;
+            const int l1 = sp_last ? cn - 1 : (cn > l0 ? cn : l0);
             const TIn *rp = rp0 + (int64_t)c0 * rstep;
             float *op = op0 + (int64_t)c0 * ostep;
-            const uint64_t valid = __builtin_amdgcn_ballot_w64(lane < cn);
+            const uint64_t valid = __builtin_amdgcn_ballot_w64(lane >= l0 && lane < l1);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                if (special) {
-                    for (int li = 0; li < cn; ++li) {
-                        float d[4];
-                        single(g, c0 + li, li, lwin, lwlo, lwhi, d);
-                        store(g, op + (int64_t)li * ostep, d);
-                    }
-                    continue;
-                }
+                if (sp_first) special_plane(g, c0, 0, op);
                 const int cl = cls_of(ls0, g);
-                const uint64_t bin = __builtin_amdgcn_ballot_w64(lane < cn && cl == IN);
-                const uint64_t bout = __builtin_amdgcn_ballot_w64(lane < cn && cl == OUT);
-                if (bout == valid) {
+                const uint64_t bin = __builtin_amdgcn_ballot_w64(lane >= l0 && lane < l1 && cl == IN);
+                const uint64_t bout =
+                    __builtin_amdgcn_ballot_w64(lane >= l0 && lane < l1 && cl == OUT);
+                if (valid == 0) {
+                    // no plane besides the special ones
+                } else if (bout == valid) {
                     // padding: zero output, nothing added to the sum
 #pragma unroll
                     for (int i = 0; i < 4; ++i) mx[g][i] = fmaxf(mx[g][i], 0.0f);
-                    float *orow = op;
+                    float *orow = op + (int64_t)l0 * ostep;
                     const float z[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-                    for (int li = 0; li < cn; ++li) {
+                    for (int li = l0; li < l1; ++li) {
                         if ((li & 3) == 0) pace_until(t0, taug, pace_pos(g, c0, cn, li));
                         store(g, orow, z);
                         orow += ostep;
                     }
                 } else if (bin == valid) {
-                    pipe_loop<UNR, false>(g, c0, cn, rp, op);
+                    pipe_loop<UNR, false>(g, c0, cn, l0, l1, rp, op);
                 } else {
-                    pipe_loop<UNR, true>(g, c0, cn, rp, op);
+                    pipe_loop<UNR, true>(g, c0, cn, l0, l1, rp, op);
                 }
+                if (sp_last) special_plane(g, c0, cn - 1, op);
             }
         }
     }
