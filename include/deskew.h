@@ -152,10 +152,13 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
  * lane, unpaced and paced at 5000-6000 GB/s with a volume (9000-12000
  * without), and the default -- for `reps`
  * rounds (3..64), a burst of 3 back-to-back launches of each shape per
- * round, round-robin after one untimed round, on the caller's own buffers
- * and stream, and returns in *tune, among the shapes whose mean time per
- * launch is within 0.5% of the fastest, the one paced slowest (*ms, host,
- * may be NULL: its mean time).  Arguments as
+ * round, round-robin after one untimed round, re-times the front runners
+ * in longer back-to-back runs, on the caller's own buffers and stream, and
+ * returns in *tune, among the shapes whose mean time per launch is within
+ * 0.5% of the fastest, the one paced slowest; with a volume its pace then
+ * steps down by at least 100 GB/s and to at most the default's 5800, clear
+ * of the pacing cliff (*ms, host, may be NULL: the mean time measured for
+ * the returned shape).  Arguments as
  * dsk_deskew_offsets_tuned.  Every trial computes the full result, so the
  * outputs may be written (with the correct values) or, when the choice is
  * already known, left untouched: call the forward with *tune afterwards.

@@ -210,25 +210,29 @@ size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &scor
     return pick;
 }
 
-// The same shape paced at least kStepDown GB/s lower (the highest such
-// candidate pace), or cand.size() for an unpaced shape or when none is
-// lower.  The chosen pace is stepped down once more: a pace the device
-// holds for every launch while tuning can fail in the runs that follow, on
-// some devices for every launch, on others for some launches only (on the
-// 512x2048 frame, 6000 GB/s: 0.827 ms in the tuner's runs and 0.90-0.97 ms
-// after; 5900 GB/s: 0.839 ms on two devices, on a third a third of its
-// launches at 0.93-0.98 ms; 5800 held on every device measured).  Falling
-// off costs 10-15%, the step about 3%.
-constexpr int kStepDown = 200;
+// The same shape paced at least kStepDown GB/s lower and at most kPaceCap
+// (the highest such candidate pace), or cand.size() for an unpaced shape or
+// when none qualifies.  The chosen pace is stepped down once more: a pace
+// the device holds for every launch while tuning can fail in the runs that
+// follow, on some devices for every launch, on others for some launches
+// only (on the 512x2048 frame, 6000 GB/s: 0.827 ms in the tuner's runs and
+// 0.90-0.97 ms after; 5900 GB/s: 0.839 ms on two devices, on a third a
+// third of its launches at 0.93-0.98 ms; 5800 held on every device
+// measured, 0.824 ms back to back).  Falling off costs 10-15%, the step
+// about 1.5%; the cap keeps the pick at or below the pace that held
+// everywhere.
+constexpr int kStepDown = 100;
+constexpr int kPaceCap = kDefaultTune.pace_gbs;
 
 size_t step_down(const std::vector<dsk_tune> &cand, const dsk_tune &t) {
     size_t pick = cand.size();
     if (t.pace_gbs <= 0) return pick;
+    const int top = std::min(t.pace_gbs - kStepDown, kPaceCap);
     for (size_t i = 0; i < cand.size(); ++i) {
         const dsk_tune &c = cand[i];
         if (c.block != t.block || c.per_thread != t.per_thread || c.unroll != t.unroll ||
             c.nt_store != t.nt_store || c.wg_per_cu != t.wg_per_cu || c.pace_gbs <= 0 ||
-            c.pace_gbs > t.pace_gbs - kStepDown)
+            c.pace_gbs > top)
             continue;
         if (pick == cand.size() || c.pace_gbs > cand[pick].pace_gbs) pick = i;
     }
