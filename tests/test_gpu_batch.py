@@ -126,6 +126,25 @@ def test_every_shape_same_bits(small, tune):
     b.close()
 
 
+@pytest.mark.parametrize("tune", [dict(block=64, per_thread=4, unroll=4, nt_store=1),
+                                  dict(block=64, per_thread=8, unroll=2, nt_store=1),
+                                  dict(block=256, per_thread=8, unroll=4, nt_store=1)])
+def test_projections_only_batch_same_bits(small, tune):
+    """A batch without volumes (one persistent launch of the projections-only
+    loop; with two groups per lane, side by side) gives each job's
+    projections bitwise as its own projections-only launch does."""
+    stacks, geoms = small
+    b = Batch(stacks, geoms, vol=False, tune=tune)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (o, s, g) in enumerate(zip(b.outputs, stacks, geoms)):
+        ref = dsk.deskew(s, *g, vol=False)
+        assert "vol" not in o or o["vol"] is None
+        for k in ("psum", "pmax"):
+            assert torch.equal(o[k], ref[k]), (tune, i, k)
+    b.close()
+
+
 @pytest.mark.parametrize("tune", [dict(block=128, per_thread=4, unroll=2, nt_store=0), None])
 def test_batch_matches_oracle(small, tune):
     """Every job of the batch -- in a given persistent shape, and in the

@@ -159,6 +159,12 @@ RAGGED = [
     (2, 2, 2, "frac", 11),         # tiny stack: scalar kernel
     (150, 6, 400, "shuffle", 12),  # offsets out of order: padding planes between others
     (200, 8, 300, "frac", 13),     # several 64-plane chunks, partial last chunk
+    # stack-end planes in the vector kernel: one plane holding both the
+    # first and the last rows, a last chunk of one plane, and a last chunk
+    # of one plane after two full ones with negative offsets
+    (1, 4, 64, "frac", 14),
+    (65, 4, 64, "frac", 15),
+    (129, 4, 96, "neg", 16),
 ]
 
 
