@@ -86,6 +86,18 @@ typedef struct {
 /* Human-readable name of a dsk_status value (static storage). */
 const char *dsk_status_string(int status);
 
+/* Bounds checks of debug builds (built with DSK_CHECK_BOUNDS=1: the library
+ * libdeskew_bounds.so).  The forward, projections-only, batch and backward
+ * kernels of such a build check every global address they read or write
+ * against the extent of the buffer their arguments describe (the stack's
+ * readable extent, the volume, the projections, the gradient volume and
+ * adjoint), count each address outside it on the device, and send that
+ * access to the extent's first element instead of out of the buffer.
+ * *count (host) receives the count since the last reset; reset != 0 zeroes
+ * it.  Returns 1 in a checking build, 0 in any other (*count = 0),
+ * DSK_EINVAL for a null count, DSK_EHIP on a HIP error.  Synchronous. */
+int dsk_debug_bounds_violations(unsigned long long *count, int reset);
+
 /* Per-image shift in pixels, Eq. 1: s = (z cos(alpha pi/180)) / p in FP64.
  * shift_px: host out.  DSK_EINVAL if a value is non-finite or p <= 0. */
 int dsk_shift_px(dsk_geom g, double *shift_px);

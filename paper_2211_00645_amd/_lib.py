@@ -47,6 +47,8 @@ class DeskewError(RuntimeError):
 
 _SIGS = {
     "dsk_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "dsk_debug_bounds_violations": (ctypes.c_int, [ctypes.POINTER(ctypes.c_ulonglong),
+                                                   ctypes.c_int]),
     "dsk_shift_px": (ctypes.c_int, [Geom, ctypes.POINTER(c_dbl)]),
     "dsk_plan": (ctypes.c_int, [Dims, c_vp, c_dbl, ctypes.POINTER(c_i64),
                                 ctypes.POINTER(c_i64)]),

@@ -8,6 +8,12 @@ host code instrumented with AddressSanitizer (every ``-fsanitize=`` flag
 goes to the host pass only; the device code is that of the normal build).
 It is loaded with ``DSK_LIB`` pointing at it and the sanitizer runtime
 preloaded, for host-only checks on a machine without a GPU.
+
+``--bounds`` (``build(bounds=True)``) builds ``libdeskew_bounds.so``: the
+debug build whose forward, batch and backward kernels check every global
+address against its buffer's extent (``DSK_CHECK_BOUNDS=1``; read the count
+with ``dsk_debug_bounds_violations``), loaded with ``DSK_LIB`` pointing at
+it.
 """
 import os
 import subprocess
@@ -20,6 +26,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdeskew.so")
 LIB_ASAN = os.path.join(PKG, "libdeskew_asan.so")
+LIB_BOUNDS = os.path.join(PKG, "libdeskew_bounds.so")
 SOURCES = ["deskew.hip", "batch.hip", "tune.hip", "rolling.hip", "view.hip", "affine.hip"]
 ARCH = os.environ.get("DSK_OFFLOAD_ARCH", "gfx950")
 FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -33,11 +40,13 @@ HOST_ASAN = "-Xarch_host -fsanitize=address -Xarch_host -fno-omit-frame-pointer 
 HOST_ASAN_LINK = "-Xarch_host -fsanitize=address -shared-libasan".split()
 
 
-def build(verbose: bool = False, asan: bool = False) -> str:
-    objdir = os.path.join(PKG, "_build", "asan" if asan else "")
+def build(verbose: bool = False, asan: bool = False, bounds: bool = False) -> str:
+    if asan and bounds:
+        raise ValueError("one variant at a time")
+    objdir = os.path.join(PKG, "_build", "asan" if asan else ("bounds" if bounds else ""))
     os.makedirs(objdir, exist_ok=True)
-    lib = LIB_ASAN if asan else LIB
-    extra = HOST_ASAN if asan else []
+    lib = LIB_ASAN if asan else (LIB_BOUNDS if bounds else LIB)
+    extra = HOST_ASAN if asan else (["-DDSK_CHECK_BOUNDS=1"] if bounds else [])
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.splitext(src)[0] + ".o")
@@ -68,4 +77,4 @@ def asan_runtime() -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv, asan="--asan" in sys.argv))
+    print(build(verbose="-v" in sys.argv, asan="--asan" in sys.argv, bounds="--bounds" in sys.argv))

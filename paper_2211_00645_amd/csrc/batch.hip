@@ -460,3 +460,9 @@ extern "C" int dsk_jobs_launch(const dsk_job *jobs, int n_jobs, void *table_host
     if (e == hipSuccess) e = launch_jobs((const JobDev *)table_dev, subs, ns, t, stream);
     return hip_status(e);
 }
+
+#if DSK_CHECK_BOUNDS
+int dsk::batch_bounds_violations(unsigned long long *count, bool reset) {
+    return read_bounds_violations(count, reset);
+}
+#endif

@@ -139,6 +139,11 @@ inline InLayout dense_layout(dsk_dims d) {
     return InLayout{d.cols, (int64_t)d.rows * d.cols, 0, (int64_t)d.planes * d.rows * d.cols};
 }
 
+#if defined(DSK_CHECK_BOUNDS) && DSK_CHECK_BOUNDS
+// Bounds-violation count of the batch kernels' translation unit (batch.hip).
+int batch_bounds_violations(unsigned long long *count, bool reset);
+#endif
+
 // Launchers (deskew.hip) used by the other translation units.
 int launch_forward(const void *in, int in_is_f32, dsk_dims d, const double *offs,
                    double shift, int64_t origin, float *vol, float *psum, float *pmax,

@@ -14,6 +14,22 @@
 
 using namespace dsk;
 
+extern "C" int dsk_debug_bounds_violations(unsigned long long *count, int reset) {
+    if (!count) return DSK_EINVAL;
+    *count = 0;
+#if DSK_CHECK_BOUNDS
+    unsigned long long a = 0, b = 0;
+    if (dsk::read_bounds_violations(&a, reset != 0) != 0 ||
+        dsk::batch_bounds_violations(&b, reset != 0) != 0)
+        return DSK_EHIP;
+    *count = a + b;
+    return 1;
+#else
+    (void)reset;
+    return 0;
+#endif
+}
+
 extern "C" const char *dsk_status_string(int status) {
     switch (status) {
     case DSK_OK: return "ok";

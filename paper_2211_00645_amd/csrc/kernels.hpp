@@ -49,6 +49,38 @@ __device__ __forceinline__ PlaneCoef plane_coef(const double *offs, double shift
     return coef_from_offset(o, origin);
 }
 
+// Bounds checks of debug builds (compiled with DSK_CHECK_BOUNDS=1).  The
+// forward and backward kernels pass every global address they read or write
+// (or, for a row read pixel by pixel, the row's whole span) through
+// bounded(), with the extent of the buffer their arguments describe.  A
+// checking build counts each address outside its extent in a per-library
+// counter (dsk_debug_bounds_violations reads it) and sends that access to
+// the extent's first element instead, so that it never touches memory
+// outside a buffer; other builds return the address unchanged.
+#ifndef DSK_CHECK_BOUNDS
+#define DSK_CHECK_BOUNDS 0
+#endif
+
+#if DSK_CHECK_BOUNDS
+static __device__ unsigned long long g_bounds_violations;
+#endif
+
+template <typename T>
+__device__ __forceinline__ T *bounded(T *p, int64_t n, const void *lo, const void *hi) {
+#if DSK_CHECK_BOUNDS
+    const char *c = (const char *)p;
+    if (c < (const char *)lo || c + n * (int64_t)sizeof(T) > (const char *)hi) {
+        atomicAdd(&g_bounds_violations, 1ull);
+        return (T *)lo;
+    }
+#else
+    (void)n;
+    (void)lo;
+    (void)hi;
+#endif
+    return p;
+}
+
 // Pixel i of a row of n, zero outside [0, n).  The load is unconditional, at
 // an index clamped into the row, so neighbouring loads of a thread are
 // issued together instead of each behind its own branch.
@@ -189,7 +221,8 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
     for (int n = 0; n < a.N; ++n) {
         const PlaneCoef pc = cc.get(n);
         const int64_t rowi = (int64_t)n * a.R + r;
-        const TIn *row = a.in + (int64_t)n * a.in_plane + (int64_t)r * a.in_row;
+        const TIn *row = bounded(a.in + (int64_t)n * a.in_plane + (int64_t)r * a.in_row, C,
+                                 a.in - a.in_lo, a.in + a.in_hi);
         float *orow = a.vol ? a.vol + rowi * W : nullptr;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
@@ -199,7 +232,8 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
                 const float hi = load_px(row, i, C);
                 const float lo = load_px(row, i - 1, C);
                 const float d = fmaf(pc.whi, hi, pc.wlo * lo);
-                if (orow) store_f32<NT>(orow + x, d);
+                if (orow)
+                    store_f32<NT>(bounded(orow + x, 1, a.vol, a.vol + (int64_t)a.N * a.R * W), d);
                 acc[j] += (double)d;
                 mx[j] = fmaxf(mx[j], d);
             }
@@ -209,8 +243,9 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
     for (int j = 0; j < J; ++j) {
         const int64_t x = x0 + threadIdx.x + (int64_t)j * BLOCK;
         if (x < W) {
-            if (a.psum) a.psum[(int64_t)r * W + x] = (float)acc[j];
-            if (a.pmax) a.pmax[(int64_t)r * W + x] = mx[j];
+            const int64_t o = (int64_t)r * W + x, rw = (int64_t)a.R * W;
+            if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc[j];
+            if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx[j];
         }
     }
 }
@@ -506,7 +541,7 @@ struct VecTile {
     __device__ __forceinline__ void fetch(int g, const TIn *rp, int v, Win &w) const {
         int off = (v >> 1) + 4 * gi[g];
         if (MASK) off = off < lo_off ? lo_off : (off > hi_off ? hi_off : off);
-        w.load(rp + off);
+        w.load(bounded(rp + off, Win::kLen, a.in - a.in_lo, a.in + a.in_hi));
     }
 
     // Interpolate one plane from its window (v its packed start/shift).
@@ -555,7 +590,7 @@ struct VecTile {
         }
         const int oc = off < lo ? lo : (off > hi ? hi : off);
         Win raw;
-        raw.load(rp + oc);
+        raw.load(bounded(rp + oc, Win::kLen, a.in - a.in_lo, a.in + a.in_hi));
         float vv[5];
         raw.extract(sh, vv);
 #pragma unroll
@@ -563,7 +598,8 @@ struct VecTile {
             if ((unsigned)(p + i) >= (unsigned)C) vv[i] = 0.0f;
         if (oc != off) {
 #pragma unroll
-            for (int i = 0; i < 5; ++i) vv[i] = load_px(rp, p + i, C);
+            for (int i = 0; i < 5; ++i)
+                vv[i] = load_px(bounded(rp, C, a.in - a.in_lo, a.in + a.in_hi), p + i, C);
         }
         interp(g, vv, wlo, whi, d);
     }
@@ -571,7 +607,8 @@ struct VecTile {
     // ---- with a volume ---------------------------------------------------
 
     __device__ __forceinline__ void store(int g, float *orow, const float d[4]) const {
-        store_f32x4<NT>(orow + xcol(g), f32x4{d[0], d[1], d[2], d[3]});
+        store_f32x4<NT>(bounded(orow + xcol(g), 4, a.vol, a.vol + (int64_t)N * a.R * W),
+                        f32x4{d[0], d[1], d[2], d[3]});
     }
 
     // Chunk planes [l0, l1) of a chunk of cn planes for group g,
@@ -877,9 +914,9 @@ struct VecTile {
         for (int g = 0; g < G; ++g) {
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int64_t o = (int64_t)r * W + xcol(g) + i;
-                if (a.psum) a.psum[o] = (float)acc[g][i];
-                if (a.pmax) a.pmax[o] = mx[g][i];
+                const int64_t o = (int64_t)r * W + xcol(g) + i, rw = (int64_t)a.R * W;
+                if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc[g][i];
+                if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx[g][i];
             }
         }
     }
@@ -915,7 +952,7 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
             const int n = min(n0 + u, a.N - 1);
             const PlaneCoef pc = cc.get(n);
             const int64_t i = (int64_t)x - pc.k;
-            const TIn *row = rp + (int64_t)n * rstep;
+            const TIn *row = bounded(rp + (int64_t)n * rstep, C, a.in - a.in_lo, a.in + a.in_hi);
             h[u] = load_px(row, i, (int64_t)C);
             l[u] = load_px(row, i - 1, (int64_t)C);
             wl[u] = pc.wlo;
@@ -934,7 +971,10 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
                 const float d = fmaf(whi[u], hi[u], wlo[u] * lo[u]);
                 acc += (double)d;
                 mx = fmaxf(mx, d);
-                if (op) store_f32<NT>(op + (int64_t)(n0 + u) * ostep, d);
+                if (op)
+                    store_f32<NT>(bounded(op + (int64_t)(n0 + u) * ostep, 1, a.vol,
+                                          a.vol + (int64_t)a.N * a.R * W),
+                                  d);
             }
         }
 #pragma unroll
@@ -946,8 +986,9 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
             whi[u] = whi2[u];
         }
     }
-    if (a.psum) a.psum[(int64_t)r * W + x] = (float)acc;
-    if (a.pmax) a.pmax[(int64_t)r * W + x] = mx;
+    const int64_t o = (int64_t)r * W + x, rw = (int64_t)a.R * W;
+    if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc;
+    if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx;
 }
 
 // Plain launches: one workgroup per (row, tile); vector launches add
@@ -1129,11 +1170,12 @@ __global__ __launch_bounds__(BLOCK) void k_backward(BwdArgs a) {
     const int64_t C = a.C, W = a.W;
     double part = 0.0;
     for (int r = r0; r < r1; ++r) {
-        const int64_t rowi = (int64_t)n * a.R + r;
-        const float *grow = a.gvol + rowi * W;
-        const float *srow = a.in + rowi * C;
+        const int64_t rowi = (int64_t)n * a.R + r, nr = (int64_t)a.N * a.R;
+        const float *grow = bounded(a.gvol + rowi * W, W, a.gvol, a.gvol + nr * W);
+        const float *srow = a.in;
+        if constexpr (GOFF) srow = bounded(a.in + rowi * C, C, a.in, a.in + nr * C);
         float *orow = nullptr;
-        if constexpr (GIN) orow = a.gin + rowi * C;
+        if constexpr (GIN) orow = bounded(a.gin + rowi * C, C, a.gin, a.gin + nr * C);
         if constexpr (VEC) {
             // 4 adjacent raw columns per thread: their 5 gradient values
             // from one 16-byte and one 4-byte load (per pixel where the
@@ -1320,5 +1362,22 @@ __global__ __launch_bounds__(256) void k_zero(T *p, int64_t n) {
     const int64_t stride = (int64_t)gridDim.x * 256;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) p[i] = T(0);
 }
+
+#if DSK_CHECK_BOUNDS
+// Host side: this translation unit's count of addresses outside their
+// extents, zeroed after reading when asked.  0, or -1 on a HIP error.
+static inline int read_bounds_violations(unsigned long long *count, bool reset) {
+    unsigned long long v = 0;
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_bounds_violations), sizeof v) != hipSuccess)
+        return -1;
+    if (reset) {
+        const unsigned long long z = 0;
+        if (hipMemcpyToSymbol(HIP_SYMBOL(g_bounds_violations), &z, sizeof z) != hipSuccess)
+            return -1;
+    }
+    *count = v;
+    return 0;
+}
+#endif
 
 }  // namespace dsk
