@@ -81,10 +81,13 @@ inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec) {
 }
 
 // Workgroups of the vector kernel for the rows' unaligned edge columns
-// (none when the width is a multiple of 4): one lane per (row, slot of 6).
+// (none when the width is a multiple of 4): one wavefront per (row, slot
+// of 6), block / 64 wavefronts per workgroup.  The kernel receives the
+// count and runs these workgroups first.
 inline int64_t edge_blocks(dsk_dims d, int64_t width, const dsk_tune &t, bool vec) {
     if (!vec || width % 4 == 0) return 0;
-    return (6 * (int64_t)d.rows + t.block - 1) / t.block;
+    const int64_t wpb = t.block / 64;
+    return (6 * (int64_t)d.rows + wpb - 1) / wpb;
 }
 
 template <int V>

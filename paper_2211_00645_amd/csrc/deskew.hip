@@ -124,11 +124,12 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
             // volume it keeps the write stream local; without one, wavefronts
             // whose plane ranges start late wait for their turn.
             if (pace_gbs > 0) {
-                // one workgroup's share of a plane's bytes, timed at pace_gbs
+                // one tile's share of a plane's bytes, timed at pace_gbs (the
+                // edge columns' workgroups are not paced)
                 const double plane_bytes = (double)a.R * a.C * sizeof(TIn) +
                                            (a.vol ? 4.0 * (double)a.R * (double)a.W : 0.0);
-                const double t = plane_bytes / (double)blocks / ((double)pace_gbs * 1e9) * 1e8 *
-                                 65536.0;
+                const double t = plane_bytes / (double)(tiles * a.R) / ((double)pace_gbs * 1e9) *
+                                 1e8 * 65536.0;
                 a.tau_wg = t >= 4.0e9 ? 4000000000u : (uint32_t)t;
                 const int64_t cap =
                     (int64_t)(a.vol ? vec_resident_per_cu<TIn, B, PT / 4, U, NT, true>()
@@ -176,12 +177,12 @@ int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLay
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
                          width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                         0u, 0u, 0};
+                         0u, 0u, 0, (int32_t)edge};
         e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
                             width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                            0u, 0u, 0};
+                            0u, 0u, 0, (int32_t)edge};
         e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);

@@ -172,6 +172,9 @@ struct FwdArgs {
     uint32_t tau256;
     uint32_t tau_wg;
     int32_t pace_cap;
+    // Workgroups of a vector launch that cover the edge columns, ahead of
+    // the tiles (the host's edge_blocks).
+    int32_t edge_wg;
 };
 
 // Plane pacing: a wavefront that reaches plane n before t0 + n * tau sleeps
@@ -445,8 +448,10 @@ struct VecTile {
         op0 = VOL ? a.vol + (int64_t)r * W : nullptr;
         tau = a.tau256;
         if (a.pace_cap > 0) {
-            const int64_t cap = a.pace_cap, batch = (int64_t)blockIdx.x / cap;
-            const int64_t left = (int64_t)gridDim.x - batch * cap;
+            // tiles start in id order after the edge columns' workgroups
+            const int64_t eb = a.edge_wg;
+            const int64_t cap = a.pace_cap, batch = ((int64_t)blockIdx.x - eb) / cap;
+            const int64_t left = (int64_t)gridDim.x - eb - batch * cap;
             const uint64_t t = ((uint64_t)a.tau_wg * (uint64_t)(left < cap ? left : cap)) >> 8;
             tau = t > 4000000000ull ? 4000000000u : (uint32_t)t;
         }
@@ -924,71 +929,50 @@ struct VecTile {
 
 // Edge columns (the at most 3 unaligned columns at each end of every row,
 // present only when W is not a multiple of 4, and then at least one per
-// row): lane e handles slot e % 6 of row e / 6; empty slots and rows past
-// the end repeat their row's first edge column (identical values to
-// identical addresses), so every lane stays active -- the per-plane
-// coefficients are shared across lanes -- and every store is unconditional.
-// Two pixel loads per plane, issued UNR planes ahead of the stores.  Same
-// per-voxel arithmetic and plane order as every other path.
-template <typename TIn, int UNR, bool NT>
-__device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
-    const int W = (int)a.W, C = a.C;
-    const int r = min(e / 6, a.R - 1);
+// row): wavefront e handles slot e % 6 of row e / 6 (empty slots exit at
+// once).  Its lanes take 64 planes at a time, one plane each: coefficients,
+// the two pixel loads and the volume store run in parallel; the FP64 sum
+// then adds the chunk's values in plane order, lane 0 first, as every other
+// path does, and the maximum takes them in the same pass.  (One lane per
+// column walking every plane alone took about 250 us for 512 planes, longer
+// than the rest of a projections-only launch.)
+template <typename TIn, bool NT>
+__device__ __forceinline__ void fwd_edge_wave(const FwdArgs<TIn> &a, int64_t e) {
+    const int W = (int)a.W, C = a.C, N = a.N;
+    const int r = (int)(e / 6);
+    if (r >= a.R) return;
     const RowGeo rg = row_geo(r, W);
-    int x = edge_col(rg, W, e - 6 * (e / 6));
-    for (int j = 0; j < 6 && x < 0; ++j) x = edge_col(rg, W, j);
-    if (x < 0) x = 0;   // unreachable when W % 4 != 0
-    const int64_t rstep = a.in_plane, ostep = (int64_t)a.R * W;
+    const int x = edge_col(rg, W, (int)(e - 6 * (e / 6)));
+    if (x < 0) return;
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t ostep = (int64_t)a.R * W;
     const TIn *rp = a.in + (int64_t)r * a.in_row;
     float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
-    CoefCache cc;
-    cc.init(a.offs, a.shift, a.origin, a.N);
     double acc = 0.0;
     float mx = -__builtin_huge_valf();
-    float lo[UNR], hi[UNR], wlo[UNR], whi[UNR];
-    auto issue = [&](int n0, float l[UNR], float h[UNR], float wl[UNR], float wh[UNR]) {
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            const int n = min(n0 + u, a.N - 1);
-            const PlaneCoef pc = cc.get(n);
-            const int64_t i = (int64_t)x - pc.k;
-            const TIn *row = bounded(rp + (int64_t)n * rstep, C, a.in - a.in_lo, a.in + a.in_hi);
-            h[u] = load_px(row, i, (int64_t)C);
-            l[u] = load_px(row, i - 1, (int64_t)C);
-            wl[u] = pc.wlo;
-            wh[u] = pc.whi;
-        }
-    };
-    issue(0, lo, hi, wlo, whi);
-#pragma unroll
-    for (int u = 0; u < UNR; ++u) asm volatile("" ::"v"(lo[u]), "v"(hi[u]));
-    for (int n0 = 0; n0 < a.N; n0 += UNR) {
-        float lo2[UNR], hi2[UNR], wlo2[UNR], whi2[UNR];
-        issue(n0 + UNR, lo2, hi2, wlo2, whi2);
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            if (n0 + u < a.N) {
-                const float d = fmaf(whi[u], hi[u], wlo[u] * lo[u]);
-                acc += (double)d;
-                mx = fmaxf(mx, d);
-                if (op)
-                    store_f32<NT>(bounded(op + (int64_t)(n0 + u) * ostep, 1, a.vol,
-                                          a.vol + (int64_t)a.N * a.R * W),
-                                  d);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-            asm volatile("" ::"v"(lo2[u]), "v"(hi2[u]));
-            lo[u] = lo2[u];
-            hi[u] = hi2[u];
-            wlo[u] = wlo2[u];
-            whi[u] = whi2[u];
+    for (int c0 = 0; c0 < N; c0 += 64) {
+        const int cn = min(64, N - c0);
+        const int n = min(c0 + lane, N - 1);
+        const PlaneCoef pc = plane_coef(a.offs, a.shift, a.origin, n);
+        const int64_t i = (int64_t)x - pc.k;
+        const TIn *row =
+            bounded(rp + (int64_t)n * a.in_plane, C, a.in - a.in_lo, a.in + a.in_hi);
+        const float d = fmaf(pc.whi, load_px(row, i, (int64_t)C),
+                             pc.wlo * load_px(row, i - 1, (int64_t)C));
+        if (op && lane < cn)
+            store_f32<NT>(bounded(op + (int64_t)n * ostep, 1, a.vol, a.vol + (int64_t)N * ostep),
+                          d);
+        for (int l = 0; l < cn; ++l) {
+            const float dl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(d), l));
+            acc += (double)dl;
+            mx = fmaxf(mx, dl);
         }
     }
-    const int64_t o = (int64_t)r * W + x, rw = (int64_t)a.R * W;
-    if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc;
-    if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx;
+    if (lane == 0) {
+        const int64_t o = (int64_t)r * W + x, rw = (int64_t)a.R * W;
+        if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc;
+        if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx;
+    }
 }
 
 // Plain launches: one workgroup per (row, tile); vector launches add
@@ -1016,8 +1000,15 @@ __device__ __forceinline__ int middle_out(int k, int T) {
 // ones fill in behind them.
 template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
 __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x, int64_t b) {
-    const int64_t main = (int64_t)a.R * tiles_x;
-    if (b < main) {
+    // the edge columns' workgroups come first: they are short and start
+    // with the first wave of tiles instead of waiting for free slots
+    const int64_t eb = a.edge_wg;
+    if (b < eb) {
+        fwd_edge_wave<TIn, NT>(a, b * (BLOCK / 64) + ((int)threadIdx.x >> 6));
+        return;
+    }
+    b -= eb;
+    {
         int r, xt;
         if constexpr (VOL) {
             r = (int)(b / tiles_x);
@@ -1029,8 +1020,6 @@ __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x
         }
         VecTile<TIn, BLOCK, G, UNR, NT, VOL> vt(a, r, xt);
         vt.run();
-    } else {
-        fwd_edge_lane<TIn, UNR, NT>(a, (int)((b - main) * BLOCK + threadIdx.x));
     }
 }
 
@@ -1109,6 +1098,7 @@ __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL, 
         a.tau256 = jb.tau256;
         a.tau_wg = 0;
         a.pace_cap = 0;
+        a.edge_wg = jb.edge_blocks;
         const int64_t lt = t - jb.tile_begin;
         if constexpr (PT >= 4) {
             if (jb.vec) {
