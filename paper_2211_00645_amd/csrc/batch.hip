@@ -78,7 +78,7 @@ int encode_table(const dsk_job *jobs, int n, const dsk_tune &t, JobDev *out, Sub
             const bool vec = vec_ok(t, j.dims, j.out_width, j.in, 0, j.vol,
                                     (int64_t)j.dims.rows * j.dims.cols);
             const int64_t tx = tiles_x(j.out_width, t, vec);
-            const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec);
+            const int64_t eb = edge_blocks(j.dims, j.out_width, t, vec, j.vol != nullptr);
             if (tx > kMaxI32) return -1;
             JobDev r;
             r.in = j.in;

@@ -81,13 +81,14 @@ inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec) {
 }
 
 // Workgroups of the vector kernel for the rows' unaligned edge columns
-// (none when the width is a multiple of 4): one wavefront per (row, slot
-// of 6), block / 64 wavefronts per workgroup.  The kernel receives the
-// count and runs these workgroups first.
-inline int64_t edge_blocks(dsk_dims d, int64_t width, const dsk_tune &t, bool vec) {
+// (none when the width is a multiple of 4), which it runs first: with a
+// volume one lane per (row, slot of 6), without one a wavefront per (row,
+// slot), block / 64 wavefronts per workgroup.  The kernel receives the
+// count.
+inline int64_t edge_blocks(dsk_dims d, int64_t width, const dsk_tune &t, bool vec, bool vol) {
     if (!vec || width % 4 == 0) return 0;
-    const int64_t wpb = t.block / 64;
-    return (6 * (int64_t)d.rows + wpb - 1) / wpb;
+    const int64_t per = vol ? t.block : t.block / 64;
+    return (6 * (int64_t)d.rows + per - 1) / per;
 }
 
 template <int V>

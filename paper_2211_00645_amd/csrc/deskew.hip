@@ -171,7 +171,7 @@ int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLay
         return DSK_ESHAPE;
     const bool vec = vec_ok(t, d, width, in, in_is_f32, vol, lay.plane);
     const int64_t tiles = tiles_x(width, t, vec);
-    const int64_t edge = edge_blocks(d, width, t, vec);
+    const int64_t edge = edge_blocks(d, width, t, vec, vol != nullptr);
     if (tiles * (int64_t)d.rows + edge > kMaxI32) return DSK_ESHAPE;
     hipError_t e;
     if (in_is_f32) {

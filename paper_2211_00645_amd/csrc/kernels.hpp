@@ -927,7 +927,80 @@ struct VecTile {
     }
 };
 
-// Edge columns (the at most 3 unaligned columns at each end of every row,
+// Edge columns of launches with a volume (the at most 3 unaligned columns
+// at each end of every row, present only when W is not a multiple of 4,
+// and then at least one per row): lane e handles slot e % 6 of row e / 6;
+// empty slots and rows past
+// the end repeat their row's first edge column (identical values to
+// identical addresses), so every lane stays active -- the per-plane
+// coefficients are shared across lanes -- and every store is unconditional.
+// Two pixel loads per plane, issued UNR planes ahead of the stores.  Same
+// per-voxel arithmetic and plane order as every other path.  Few lanes
+// trickle through the planes beside the paced tiles for most of the
+// launch; a burst of edge work at the start (the wavefront form below)
+// puts the tiles behind their pacing schedule for good.
+template <typename TIn, int UNR, bool NT>
+__device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
+    const int W = (int)a.W, C = a.C;
+    const int r = min(e / 6, a.R - 1);
+    const RowGeo rg = row_geo(r, W);
+    int x = edge_col(rg, W, e - 6 * (e / 6));
+    for (int j = 0; j < 6 && x < 0; ++j) x = edge_col(rg, W, j);
+    if (x < 0) x = 0;   // unreachable when W % 4 != 0
+    const int64_t rstep = a.in_plane, ostep = (int64_t)a.R * W;
+    const TIn *rp = a.in + (int64_t)r * a.in_row;
+    float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
+    CoefCache cc;
+    cc.init(a.offs, a.shift, a.origin, a.N);
+    double acc = 0.0;
+    float mx = -__builtin_huge_valf();
+    float lo[UNR], hi[UNR], wlo[UNR], whi[UNR];
+    auto issue = [&](int n0, float l[UNR], float h[UNR], float wl[UNR], float wh[UNR]) {
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            const int n = min(n0 + u, a.N - 1);
+            const PlaneCoef pc = cc.get(n);
+            const int64_t i = (int64_t)x - pc.k;
+            const TIn *row = bounded(rp + (int64_t)n * rstep, C, a.in - a.in_lo, a.in + a.in_hi);
+            h[u] = load_px(row, i, (int64_t)C);
+            l[u] = load_px(row, i - 1, (int64_t)C);
+            wl[u] = pc.wlo;
+            wh[u] = pc.whi;
+        }
+    };
+    issue(0, lo, hi, wlo, whi);
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) asm volatile("" ::"v"(lo[u]), "v"(hi[u]));
+    for (int n0 = 0; n0 < a.N; n0 += UNR) {
+        float lo2[UNR], hi2[UNR], wlo2[UNR], whi2[UNR];
+        issue(n0 + UNR, lo2, hi2, wlo2, whi2);
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            if (n0 + u < a.N) {
+                const float d = fmaf(whi[u], hi[u], wlo[u] * lo[u]);
+                acc += (double)d;
+                mx = fmaxf(mx, d);
+                if (op)
+                    store_f32<NT>(bounded(op + (int64_t)(n0 + u) * ostep, 1, a.vol,
+                                          a.vol + (int64_t)a.N * a.R * W),
+                                  d);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+            asm volatile("" ::"v"(lo2[u]), "v"(hi2[u]));
+            lo[u] = lo2[u];
+            hi[u] = hi2[u];
+            wlo[u] = wlo2[u];
+            whi[u] = whi2[u];
+        }
+    }
+    const int64_t o = (int64_t)r * W + x, rw = (int64_t)a.R * W;
+    if (a.psum) *bounded(a.psum + o, 1, a.psum, a.psum + rw) = (float)acc;
+    if (a.pmax) *bounded(a.pmax + o, 1, a.pmax, a.pmax + rw) = mx;
+}
+
+// Edge columns of launches without a volume (the at most 3 unaligned columns at each end of every row,
 // present only when W is not a multiple of 4, and then at least one per
 // row): wavefront e handles slot e % 6 of row e / 6 (empty slots exit at
 // once).  Its lanes take 64 planes at a time, one plane each: coefficients,
@@ -1004,7 +1077,10 @@ __device__ __forceinline__ void fwd_vec_block(const FwdArgs<TIn> &a, int tiles_x
     // with the first wave of tiles instead of waiting for free slots
     const int64_t eb = a.edge_wg;
     if (b < eb) {
-        fwd_edge_wave<TIn, NT>(a, b * (BLOCK / 64) + ((int)threadIdx.x >> 6));
+        if constexpr (VOL)
+            fwd_edge_lane<TIn, UNR, NT>(a, (int)(b * BLOCK + threadIdx.x));
+        else
+            fwd_edge_wave<TIn, NT>(a, b * (BLOCK / 64) + ((int)threadIdx.x >> 6));
         return;
     }
     b -= eb;
@@ -1042,8 +1118,12 @@ constexpr int vec_waves_per_eu(int g, int unr, bool vol, int in_bytes) {
 template <typename TIn, int BLOCK, int G, int UNR, bool NT, bool VOL>
 __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(G, UNR, VOL, (int)sizeof(TIn))) void k_forward_vec(
     FwdArgs<TIn> a, int tiles_x) {
-    fwd_vec_block<TIn, BLOCK, G, UNR, NT, VOL>(
-        a, tiles_x, VOL ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x);
+    // edge-column workgroups first, in dispatch order (spread over the
+    // XCDs); with a volume the tiles after them are remapped so that each
+    // XCD gets a contiguous range of them
+    const int64_t eb = a.edge_wg, d = blockIdx.x;
+    const int64_t lb = (VOL && d >= eb) ? eb + xcd_remap(d - eb, (int64_t)gridDim.x - eb) : d;
+    fwd_vec_block<TIn, BLOCK, G, UNR, NT, VOL>(a, tiles_x, lb);
 }
 
 // Job record of the persistent ragged-batch kernel (device-resident table).
