@@ -9,10 +9,13 @@
 //
 // The output is several times the remap's volume and each output row
 // crosses many images, so a plain gather would fetch a cache line per pixel.
-// The main kernel (k_affine_ring) keeps the images a 64-column strip needs
-// in an LDS ring while it sweeps y; the one-shot kernel (k_affine, one lane
-// per 4 output columns in output order) covers the geometries the ring does
-// not (the band moving a whole image or more per y, or wider than the ring).
+// The kernels keep the images a 64-column strip needs in an LDS ring while
+// they sweep y.  The main one (k_affine_rows) sweeps four rows of a strip at
+// once, so that each voxel's weights, which depend on (y, z) only, serve four
+// voxels; k_affine_ring (one row, a lane per column) covers the layouts it
+// does not take, and the one-shot kernel (k_affine, one lane per 4 output
+// columns in output order) the geometries no ring takes (the band moving a
+// whole image or more per y, or wider than the ring).
 #include <cmath>
 #include <cstdint>
 
@@ -108,17 +111,8 @@ struct RingArgs {
 // look-ahead.  The ring has 32 rows plus a copy of row 0 after row 31, so
 // the two images a voxel needs are always in consecutive rows.  The host
 // keeps every u within +-1e9, so floors fit an int.
-//
-// WIDE (YQ = 4, columns a multiple of 4, volume 16-byte aligned): the four
-// y values of a step go to four groups of 16 lanes, each lane computing 4
-// adjacent columns of its y and storing them with one 16-byte store.  A
-// lane per column would store 4 bytes per lane per y, and then the
-// address/data path of the stores, not memory, bounds the kernel (measured
-// on 512x512x2048: texture data unit busy 87% of the time, 3.5 TB/s); a
-// 16-byte store moves four times the bytes per store instruction.
-template <typename TIn, int YQ, int AHEAD, bool WIDE = false>
+template <typename TIn, int YQ, int AHEAD>
 __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
-    static_assert(!WIDE || YQ == 4, "the wide layout is 4 y values x 16 lanes");
     constexpr int NF = YQ == 1 ? 1 : 2;        // fetches per step
     __shared__ float ring[33 * 64];
     const AffArgs<TIn> &a = ra.a;
@@ -132,11 +126,6 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
     const int ze = zb + 63 < a.C ? zb + 63 : a.C - 1;
     const bool zok = zb + lane < a.C;
     const int zc = zok ? zb + lane : ze;       // the column this lane reads and writes
-    // WIDE: this lane's y within a step and its 4 columns (lanes past the
-    // last group repeat it: identical values to identical addresses)
-    const int yq = lane >> 4;
-    const int ngrp = (ze - zb + 1) / 4;
-    const int zq = zb + 4 * ((lane & 15) < ngrp ? (lane & 15) : ngrp - 1);
     const int64_t y_lo = yc * ra.ychunk;
     const int64_t y_hi = (y_lo + ra.ychunk < a.ny ? y_lo + ra.ychunk : a.ny);
     const int ny_c = (int)(y_hi - y_lo);
@@ -149,9 +138,6 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
     const int64_t y_first = up ? y_lo : y_hi - 1;
     const double ds = fabs(a.uy);
     const double uzl = __dmul_rn((double)zc, a.uz);
-    double uzq[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) uzq[i] = WIDE ? __dmul_rn((double)(zq + i), a.uz) : 0.0;
     const double uzb = __dmul_rn((double)zb, a.uz), uze = __dmul_rn((double)ze, a.uz);
     const double uz_min = uzb < uze ? uzb : uze, uz_max = uzb < uze ? uze : uzb;
     auto fl = [](double v) { return (int)floor(v); };
@@ -245,42 +231,7 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
             qn[k][i] = mi;
         }
         have = m;
-        if constexpr (WIDE) {
-            // this lane's y: the same chain of adds as the band's bookkeeping,
-            // picked without a branch (integer selects on the two halves)
-            const double p1 = __dadd_rn(p0, ds), p2 = __dadd_rn(p1, ds), p3 = __dadd_rn(p2, ds);
-            int plo = __double2loint(p0), phi = __double2hiint(p0);
-            plo = yq == 1 ? __double2loint(p1) : plo;
-            phi = yq == 1 ? __double2hiint(p1) : phi;
-            plo = yq == 2 ? __double2loint(p2) : plo;
-            phi = yq == 2 ? __double2hiint(p2) : phi;
-            plo = yq == 3 ? __double2loint(p3) : plo;
-            phi = yq == 3 ? __double2hiint(p3) : phi;
-            const double p = __hiloint2double(phi, plo);
-            // all ring reads of the step before any is used, so their
-            // latencies overlap
-            int ri[4];
-            float wl[4], wh[4], lo[4], hi[4], v[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const double u = __dsub_rn(p, uzq[i]);
-                const double fi = floor(u);
-                ri[i] = ((int)fi & 31) * 64 + (zq - zb + i);
-                const double f = __dsub_rn(u, fi);
-                wl[i] = (float)f;
-                wh[i] = (float)__dsub_rn(1.0, f);
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                lo[i] = ring[ri[i]];
-                hi[i] = ring[ri[i] + 64];
-            }
-#pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = fmaf(wl[i], hi[i], wh[i] * lo[i]);
-            if (!tail || j * 4 + yq < ny_c)
-                store_f32x4<true>(orow + (int64_t)yq * ostep + zq, f32x4{v[0], v[1], v[2], v[3]});
-            orow += 4 * ostep;
-        } else {
+        {
             double p = p0;
 #pragma unroll
             for (int i = 0; i < YQ; ++i) {
@@ -310,6 +261,233 @@ __global__ __launch_bounds__(64) void k_affine_ring(RingArgs<TIn> ra) {
 #pragma unroll
     for (int k = 0; k < AHEAD; ++k)
         if (full + k < steps) step(k, full + k, true);
+}
+
+// Row kernel: persistent wavefronts, each taking work items (y range, strip
+// of kAffRows rows x 64 columns) in turn, consecutive wavefronts on
+// neighbouring strips of one y range, so that the wavefronts write
+// neighbouring output rows of the same planes.  Each sweeps its y range in
+// the direction in which u grows, 4 y values per step:
+//  * the weights of a voxel depend on (y, z) only: lane group y (16 lanes,
+//    4 adjacent columns each) computes them once, in FP64 as the ring
+//    kernel does, and applies them to all kAffRows rows;
+//  * the rows share one LDS ring of 32 image rows with the rows interleaved
+//    (ring[((n mod 32) * 64 + column) * kAffRows + row]), so one 16-byte LDS
+//    read returns an image's value in all rows and one 16-byte write enters
+//    it;
+//  * the at most 2 images a step needs first arrive in one 4-byte load per
+//    row: the wavefront's halves read the two images, 2 columns per lane,
+//    AHEAD steps before the step that needs them;
+//  * the y chain P(y + 1) = P(y) + |uy| restarts from the exact
+//    u0 + y uy every kAffRestart values of the sweep (as the ring kernel's
+//    512-y work items do), so its rounding never accumulates over more than
+//    that many adds.
+// Requires (host): C a multiple of 4, the stack 4-byte and the volume 16-byte
+// aligned, at most 2 new images per step and the band within the ring
+// (the YQ = 4 ring conditions).  Rows past the last repeat the last row
+// (identical values to identical addresses).
+constexpr int kAffRows = 4;
+constexpr int kAffRestart = 512;
+constexpr int kAffRowsAhead = 4;
+// Workgroups per compute unit: the 32 KB ring allows 5; 4 (one wavefront
+// per SIMD) gave each of them the same number of work items on the
+// 512x512x2048 stack (4096 strips over 1024 wavefronts).  Measured there:
+// 3.37 ms against 4.40 ms for the lane-per-column ring kernel.
+constexpr int kAffRowsPerCU = 4;
+
+struct RowsArgs {
+    AffArgs<uint16_t> a;
+    int64_t ylen;      // y values per work item, a multiple of kAffRestart
+    int64_t strips;    // ceil(R / kAffRows) * ztiles
+    int64_t items;     // strips * ceil(ny / ylen)
+    int32_t ztiles;
+};
+
+__device__ __forceinline__ void affine_rows_item(const AffArgs<uint16_t> &a, float *ring, int x0,
+                                                 int zb, int64_t y_lo, int64_t y_hi) {
+    constexpr int AHEAD = kAffRowsAhead;
+    constexpr int NR = kAffRows;
+    const int lane = (int)threadIdx.x;
+    const int ze = zb + 63 < a.C ? zb + 63 : a.C - 1;
+    // this lane's y within a step and its 4 columns (lanes past the last
+    // group repeat it)
+    const int yq = lane >> 4;
+    const int ngrp = (ze - zb + 1) / 4;
+    const int zq = zb + 4 * ((lane & 15) < ngrp ? (lane & 15) : ngrp - 1);
+    const int ny_c = (int)(y_hi - y_lo);
+    const int steps = (ny_c + 3) / 4;
+    const bool up = a.uy > 0.0;
+    const int64_t y_first = up ? y_lo : y_hi - 1;
+    const double ds = fabs(a.uy);
+    double uzq[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) uzq[i] = __dmul_rn((double)(zq + i), a.uz);
+    const double uzb = __dmul_rn((double)zb, a.uz), uze = __dmul_rn((double)ze, a.uz);
+    const double uz_min = uzb < uze ? uzb : uze, uz_max = uzb < uze ? uze : uzb;
+    auto fl = [](double v) { return (int)floor(v); };
+    const int64_t plane = (int64_t)a.R * a.C;
+    // loads: half h of the wavefront reads the step's image h, columns
+    // pcol, pcol + 1 (the last pair repeated past the strip's end)
+    const int pl = 2 * (lane & 31);
+    const bool second = lane >= 32;
+    const int pcol = zb + pl <= a.C - 2 ? zb + pl : a.C - 2;
+    const uint16_t *rowp[NR];
+    float *orow[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int x = x0 + r < a.R ? x0 + r : a.R - 1;
+        rowp[r] = a.in + (int64_t)x * a.C + pcol;
+        orow[r] = a.vol + (y_first * a.R + x) * (int64_t)a.C;
+    }
+    // images outside the stack read image 0 or N-1 and enter the ring
+    // scaled by 0
+    auto load2 = [&](int r, int m0, int m1) {
+        const int n = second ? m1 : m0;
+        const int64_t nc = n < 0 ? 0 : (n >= a.N ? a.N - 1 : n);
+        return *(const uint32_t *)(rowp[r] + nc * plane);
+    };
+    auto put2 = [&](int m0, int m1, const uint32_t *v) {
+        const int n = second ? m1 : m0;
+        const float sc = (n >= 0 && n < a.N) ? 1.0f : 0.0f;
+        float *p = ring + ((n & 31) * 64 + pl) * NR;
+        f32x4 e, o;
+        e.x = (float)(v[0] & 0xffffu) * sc;
+        e.y = (float)(v[1] & 0xffffu) * sc;
+        e.z = (float)(v[2] & 0xffffu) * sc;
+        e.w = (float)(v[3] & 0xffffu) * sc;
+        o.x = (float)(v[0] >> 16) * sc;
+        o.y = (float)(v[1] >> 16) * sc;
+        o.z = (float)(v[2] >> 16) * sc;
+        o.w = (float)(v[3] >> 16) * sc;
+        *(f32x4 *)p = e;
+        *(f32x4 *)(p + NR) = o;
+    };
+    // the chain: the step prepared next starts at sweep index 4 * prep; each
+    // step's 4 chain values are computed once, when it is prepared AHEAD
+    // steps ahead, and each lane keeps the one of its y
+    double Pc = 0.0, cfirst = 0.0;
+    double Psel[AHEAD];
+    int top = 0;           // last image the prepared step needs
+    auto prepare = [&](int k, int prep) {
+        const int i0 = 4 * prep;
+        const int64_t y = up ? y_first + i0 : y_first - i0;
+        const double c0 = (i0 % kAffRestart == 0) ? __dadd_rn(a.u0, __dmul_rn((double)y, a.uy)) : Pc;
+        const double c1 = __dadd_rn(c0, ds), c2 = __dadd_rn(c1, ds), c3 = __dadd_rn(c2, ds);
+        // this lane's value, picked without a branch (integer selects on the
+        // two halves)
+        int plo = __double2loint(c0), phi = __double2hiint(c0);
+        plo = yq == 1 ? __double2loint(c1) : plo;
+        phi = yq == 1 ? __double2hiint(c1) : phi;
+        plo = yq == 2 ? __double2loint(c2) : plo;
+        phi = yq == 2 ? __double2hiint(c2) : phi;
+        plo = yq == 3 ? __double2loint(c3) : plo;
+        phi = yq == 3 ? __double2hiint(c3) : phi;
+        Psel[k] = __hiloint2double(phi, plo);
+        cfirst = c0;
+        top = fl(__dsub_rn(c3, uz_min)) + 1;
+        Pc = __dadd_rn(c3, ds);
+    };
+    prepare(0, 0);
+    const int lo0 = fl(__dsub_rn(cfirst, uz_max));   // the first step's lowest image
+#pragma unroll
+    for (int k = 1; k < AHEAD; ++k)
+        if (k < steps) prepare(k, k);
+    // fill: the band of the first AHEAD steps, 8 images per round
+    for (int n = lo0; n <= top; n += 8) {
+        uint32_t t[4][NR];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m0 = n + 2 * i <= top ? n + 2 * i : top;
+            const int m1 = n + 2 * i + 1 <= top ? n + 2 * i + 1 : top;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) t[i][r] = load2(r, m0, m1);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int m0 = n + 2 * i <= top ? n + 2 * i : top;
+            const int m1 = n + 2 * i + 1 <= top ? n + 2 * i + 1 : top;
+            put2(m0, m1, t[i]);
+        }
+    }
+    int have = top;
+    uint32_t q[AHEAD][NR];
+    int qn[AHEAD][2];
+#pragma unroll
+    for (int k = 0; k < AHEAD; ++k) {
+        qn[k][0] = qn[k][1] = have;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) q[k][r] = 0;
+    }
+    const int64_t ostep = (up ? 1 : -1) * plane;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) orow[r] += (int64_t)yq * ostep + zq;
+
+    auto step = [&](int k, int j, bool tail) {
+        // the images fetched AHEAD steps ago enter the ring
+        if (j >= AHEAD) put2(qn[k][0], qn[k][1], q[k]);
+        const double p = Psel[k];
+        int m = have;
+        if (j + AHEAD < steps) {
+            prepare(k, j + AHEAD);
+            m = top > have ? top : have;
+        }
+        // at most 2 new images: have + 1 .. m (or again the newest)
+        const int mi0 = have + 1 <= m ? have + 1 : m, mi1 = have + 2 <= m ? have + 2 : m;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) q[k][r] = load2(r, mi0, mi1);
+        qn[k][0] = mi0;
+        qn[k][1] = mi1;
+        have = m;
+        float wl[4], wh[4];
+        f32x4 lo[4], hi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double u = __dsub_rn(p, uzq[i]);
+            const double fi = floor(u);
+            const int n0 = (int)fi;
+            const int c = zq - zb + i;
+            const double f = __dsub_rn(u, fi);
+            // both weights rounded once from FP64
+            wl[i] = (float)f;
+            wh[i] = (float)__dsub_rn(1.0, f);
+            lo[i] = *(const f32x4 *)(ring + ((n0 & 31) * 64 + c) * NR);
+            hi[i] = *(const f32x4 *)(ring + (((n0 + 1) & 31) * 64 + c) * NR);
+        }
+        f32x4 v[NR];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            v[0][i] = fmaf(wl[i], hi[i].x, wh[i] * lo[i].x);
+            v[1][i] = fmaf(wl[i], hi[i].y, wh[i] * lo[i].y);
+            v[2][i] = fmaf(wl[i], hi[i].z, wh[i] * lo[i].z);
+            v[3][i] = fmaf(wl[i], hi[i].w, wh[i] * lo[i].w);
+        }
+        if (!tail || j * 4 + yq < ny_c) {
+#pragma unroll
+            for (int r = 0; r < NR; ++r) store_f32x4<true>(orow[r], v[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; ++r) orow[r] += 4 * ostep;
+    };
+    const int full = (ny_c / 4) / AHEAD * AHEAD;   // steps with all 4 y values, whole groups
+    for (int j0 = 0; j0 < full; j0 += AHEAD) {
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) step(k, j0 + k, false);
+    }
+#pragma unroll
+    for (int k = 0; k < AHEAD; ++k)
+        if (full + k < steps) step(k, full + k, true);
+}
+
+__global__ __launch_bounds__(64) void k_affine_rows(RowsArgs ra) {
+    __shared__ __align__(16) float ring[kAffRows * 32 * 64];
+    for (int64_t it = blockIdx.x; it < ra.items; it += gridDim.x) {
+        const int64_t c = it / ra.strips, s = it - c * ra.strips;
+        const int xi = (int)(s / ra.ztiles);
+        const int zb = 64 * (int)(s - (int64_t)xi * ra.ztiles);
+        const int64_t y_lo = c * ra.ylen;
+        const int64_t y_hi = y_lo + ra.ylen < ra.a.ny ? y_lo + ra.ylen : ra.a.ny;
+        affine_rows_item(ra.a, ring, xi * kAffRows, zb, y_lo, y_hi);
+    }
 }
 
 bool geom_ok(dsk_geom g) {
@@ -367,13 +545,26 @@ extern "C" int dsk_affine_u16(const uint16_t *in, dsk_dims d, dsk_geom g, double
     bool u_ok = true;
     for (double v : ue) u_ok = u_ok && std::fabs(v) < 1.0e9;
     if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.499 && band4 <= 32.0) {
+        if (d.cols % 4 == 0 && ((uintptr_t)vol & 15) == 0 && ((uintptr_t)in & 3) == 0 &&
+            ny < (int64_t(1) << 30)) {
+            // row kernel: persistent, kAffRows-row strips; when the strips
+            // do not fill the resident wavefronts, the y range is split in
+            // multiples of kAffRestart
+            const int64_t strips = ((int64_t)d.rows + kAffRows - 1) / kAffRows * ztiles;
+            const int64_t resident = (int64_t)kAffRowsPerCU * device_cus();
+            const int64_t ychunks = (ny + kAffRestart - 1) / kAffRestart;
+            int64_t split = strips >= resident ? 1 : (resident + strips - 1) / strips;
+            split = split < ychunks ? split : ychunks;
+            const int64_t ylen = (ychunks + split - 1) / split * kAffRestart;
+            const int64_t items = strips * ((ny + ylen - 1) / ylen);
+            const int64_t grid = items < resident ? items : resident;
+            const RowsArgs ra{a, ylen, strips, items, ztiles};
+            hipLaunchKernelGGL(k_affine_rows, dim3((unsigned)grid), dim3(64), 0, stream, ra);
+            return hip_status(hipGetLastError());
+        }
         const RingArgs<uint16_t> ra{a, ychunk, ztiles};
-        if (d.cols % 4 == 0 && ((uintptr_t)vol & 15) == 0)
-            hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4, true>), dim3((unsigned)blocks),
-                               dim3(64), 0, stream, ra);
-        else
-            hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4>), dim3((unsigned)blocks), dim3(64),
-                               0, stream, ra);
+        hipLaunchKernelGGL((k_affine_ring<uint16_t, 4, 4>), dim3((unsigned)blocks), dim3(64), 0,
+                           stream, ra);
         return hip_status(hipGetLastError());
     }
     if (u_ok && blocks < kMaxI32 && std::fabs(a.uy) <= 0.999 && band1 <= 32.0) {

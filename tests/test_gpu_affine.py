@@ -37,6 +37,9 @@ def test_index_shear_case_is_bitwise():
     ((90, 4, 48), 20.0, 0.15, 0.3),           # small step: columns cross several images
     ((50, 20, 200), 35.0, 0.4, 0.115),        # 4 columns per lane, last column tile partial
     ((70, 6, 40), 30.0, 0.4, 0.09),           # 4 columns per lane, one partial tile
+    ((200, 7, 132), 35.0, 0.4, 0.02),         # 4-row strips, 3 rows past the last; 9 y ranges
+    ((200, 5, 64), 35.0, -0.4, 0.03),         # reversed scan, sweeps longer than 512 y
+    ((3, 9, 16), 35.0, 0.4, 0.115),           # fewer y values than one step needs
 ])
 def test_matches_oracle(shape, ang, step, dy):
     st = synth.blob_stack(shape, 20, 5, device=DEV)
@@ -45,6 +48,25 @@ def test_matches_oracle(shape, ang, step, dy):
     o, (oy0, ony) = oracle.affine(st.cpu().numpy(), ang, step, 0.115, dy)
     assert (y0, ny) == (oy0, ony)
     _close(v.cpu().numpy(), o)
+
+
+@pytest.mark.parametrize("shape,dy", [((96, 10, 200), 0.03), ((64, 128, 256), 0.115)])
+def test_row_kernel_matches_column_kernel(shape, dy):
+    """A stack 2 bytes off 4-byte alignment takes the lane-per-column ring
+    kernel; the aligned copy takes the 4-row kernel.  Sweeping up, both
+    follow the same FP64 chain (restarted from u0 + y uy every 512 y) and
+    weights: bitwise equal volumes."""
+    st = synth.blob_stack(shape, 20, 9, device=DEV)
+    n = st.numel()
+    buf = torch.empty(n + 1, dtype=torch.uint16, device=DEV)
+    buf[1:].copy_(st.reshape(-1))
+    odd = buf[1:].view(shape)
+    assert odd.data_ptr() % 4 == 2 and st.data_ptr() % 4 == 0
+    a, (y0, ny) = dsk.affine(st, 35.0, 0.4, 0.115, dy)
+    b, _ = dsk.affine(odd, 35.0, 0.4, 0.115, dy)
+    torch.cuda.synchronize()
+    assert ny > 512 or shape[0] == 64
+    assert torch.equal(a, b)
 
 
 def test_full_size_sampled_slices():
