@@ -119,26 +119,59 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
             // launches without a volume only read: no store kind to choose
             auto kern = a.vol ? k_forward_vec<TIn, B, PT / 4, U, NT, true>
                               : k_forward_vec<TIn, B, PT / 4, U, false, false>;
-            const int64_t blocks = tiles * a.R + edge;
             // Pacing holds every wavefront to one plane schedule: with a
             // volume it keeps the write stream local; without one, wavefronts
             // whose plane ranges start late wait for their turn.
-            if (pace_gbs > 0) {
-                // one tile's share of a plane's bytes, timed at pace_gbs (the
-                // edge columns' workgroups are not paced)
-                const double plane_bytes = (double)a.R * a.C * sizeof(TIn) +
-                                           (a.vol ? 4.0 * (double)a.R * (double)a.W : 0.0);
-                const double t = plane_bytes / (double)(tiles * a.R) / ((double)pace_gbs * 1e9) *
-                                 1e8 * 65536.0;
-                a.tau_wg = t >= 4.0e9 ? 4000000000u : (uint32_t)t;
-                const int64_t cap =
-                    (int64_t)(a.vol ? vec_resident_per_cu<TIn, B, PT / 4, U, NT, true>()
-                                    : vec_resident_per_cu<TIn, B, PT / 4, U, false, false>()) *
-                    device_cus();
-                a.pace_cap = (int32_t)(cap < 1 ? 1 : (cap > kMaxI32 ? kMaxI32 : cap));
+            int64_t cap = 0;
+            if (pace_gbs > 0)
+                cap = (int64_t)(a.vol ? vec_resident_per_cu<TIn, B, PT / 4, U, NT, true>()
+                                      : vec_resident_per_cu<TIn, B, PT / 4, U, false, false>()) *
+                      device_cus();
+            auto launch_rows = [&](FwdArgs<TIn> f, int64_t f_edge) {
+                if (pace_gbs > 0) {
+                    // one tile's share of a plane's bytes, timed at pace_gbs
+                    // (the edge columns' workgroups are not paced)
+                    const double plane_bytes = (double)f.R * f.C * sizeof(TIn) +
+                                               (f.vol ? 4.0 * (double)f.R * (double)f.W : 0.0);
+                    const double t = plane_bytes / (double)(tiles * f.R) /
+                                     ((double)pace_gbs * 1e9) * 1e8 * 65536.0;
+                    f.tau_wg = t >= 4.0e9 ? 4000000000u : (uint32_t)t;
+                    f.pace_cap = (int32_t)(cap < 1 ? 1 : (cap > kMaxI32 ? kMaxI32 : cap));
+                }
+                f.edge_wg = (int32_t)f_edge;
+                hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * f.R + f_edge)), block, 0, s, f,
+                                   (int)tiles);
+                return hipGetLastError();
+            };
+            // A paced frame with a volume and more tiles than resident
+            // workgroups goes out as bands of rows that each fit, one launch
+            // after another: a second round of tiles starting as the first
+            // ones end would fall behind their schedule and spread the write
+            // stream over the volume.  Bands start at multiples of 4 rows, so
+            // every row keeps its residues mod 4 (r W and r in_row) and with
+            // them the kernel's alignment.
+            const int64_t band = cap / tiles / 4 * 4;
+            if (a.vol && pace_gbs > 0 && tiles * a.R > cap && band >= 4) {
+                const int64_t nb = (a.R + band - 1) / band;
+                const int64_t rows = ((a.R + nb - 1) / nb + 3) / 4 * 4;
+                const int64_t per = B;   // edge lanes per workgroup with a volume
+                for (int64_t r0 = 0; r0 < a.R; r0 += rows) {
+                    FwdArgs<TIn> f = a;
+                    const int64_t nr = a.R - r0 < rows ? a.R - r0 : rows;
+                    const int64_t in_off = r0 * a.in_row;
+                    f.in = a.in + in_off;
+                    f.in_lo = a.in_lo + in_off;
+                    f.in_hi = a.in_hi - in_off;
+                    f.R = (int32_t)nr;
+                    f.vol = a.vol + r0 * a.W;
+                    f.psum = a.psum ? a.psum + r0 * a.W : nullptr;
+                    f.pmax = a.pmax ? a.pmax + r0 * a.W : nullptr;
+                    const hipError_t e = launch_rows(f, edge > 0 ? (6 * nr + per - 1) / per : 0);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
             }
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), block, 0, s, a, (int)tiles);
-            return hipGetLastError();
+            return launch_rows(a, edge);
         }
     }
     hipLaunchKernelGGL((k_forward_scalar<TIn, B, PT, NT>), dim3((unsigned)(tiles * a.R)), block,
@@ -177,12 +210,12 @@ int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLay
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
                          width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                         0u, 0u, 0, (int32_t)edge};
+                         0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width};
         e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
                             width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                            0u, 0u, 0, (int32_t)edge};
+                            0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width};
         e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);

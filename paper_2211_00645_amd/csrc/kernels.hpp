@@ -175,6 +175,10 @@ struct FwdArgs {
     // Workgroups of a vector launch that cover the edge columns, ahead of
     // the tiles (the host's edge_blocks).
     int32_t edge_wg;
+    // Volume plane pitch in elements: R * W, or the whole frame's when the
+    // launch covers a band of its rows (vol, psum and pmax then point at the
+    // band's first row).
+    int64_t vol_plane;
 };
 
 // Plane pacing: a wavefront that reaches plane n before t0 + n * tau sleeps
@@ -223,10 +227,9 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
     cc.init(a.offs, a.shift, a.origin, a.N);
     for (int n = 0; n < a.N; ++n) {
         const PlaneCoef pc = cc.get(n);
-        const int64_t rowi = (int64_t)n * a.R + r;
         const TIn *row = bounded(a.in + (int64_t)n * a.in_plane + (int64_t)r * a.in_row, C,
                                  a.in - a.in_lo, a.in + a.in_hi);
-        float *orow = a.vol ? a.vol + rowi * W : nullptr;
+        float *orow = a.vol ? a.vol + (int64_t)n * a.vol_plane + (int64_t)r * W : nullptr;
 #pragma unroll
         for (int j = 0; j < J; ++j) {
             const int64_t x = x0 + threadIdx.x + (int64_t)j * BLOCK;
@@ -236,7 +239,7 @@ __device__ __forceinline__ void fwd_tile_scalar(const FwdArgs<TIn> &a, int r, in
                 const float lo = load_px(row, i - 1, C);
                 const float d = fmaf(pc.whi, hi, pc.wlo * lo);
                 if (orow)
-                    store_f32<NT>(bounded(orow + x, 1, a.vol, a.vol + (int64_t)a.N * a.R * W), d);
+                    store_f32<NT>(bounded(orow + x, 1, a.vol, a.vol + (int64_t)a.N * a.vol_plane), d);
                 acc[j] += (double)d;
                 mx[j] = fmaxf(mx[j], d);
             }
@@ -428,7 +431,7 @@ struct VecTile {
         ca = rg.ca;
         ng = rg.ng;
         rstep = a.in_plane;
-        ostep = (int64_t)a.R * W;
+        ostep = a.vol_plane;
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
         lane = (int)threadIdx.x & 63;
         const int base = tile * BLOCK * G;
@@ -612,7 +615,7 @@ struct VecTile {
     // ---- with a volume ---------------------------------------------------
 
     __device__ __forceinline__ void store(int g, float *orow, const float d[4]) const {
-        store_f32x4<NT>(bounded(orow + xcol(g), 4, a.vol, a.vol + (int64_t)N * a.R * W),
+        store_f32x4<NT>(bounded(orow + xcol(g), 4, a.vol, a.vol + (int64_t)N * a.vol_plane),
                         f32x4{d[0], d[1], d[2], d[3]});
     }
 
@@ -947,7 +950,7 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
     int x = edge_col(rg, W, e - 6 * (e / 6));
     for (int j = 0; j < 6 && x < 0; ++j) x = edge_col(rg, W, j);
     if (x < 0) x = 0;   // unreachable when W % 4 != 0
-    const int64_t rstep = a.in_plane, ostep = (int64_t)a.R * W;
+    const int64_t rstep = a.in_plane, ostep = a.vol_plane;
     const TIn *rp = a.in + (int64_t)r * a.in_row;
     float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
     CoefCache cc;
@@ -982,7 +985,7 @@ __device__ __forceinline__ void fwd_edge_lane(const FwdArgs<TIn> &a, int e) {
                 mx = fmaxf(mx, d);
                 if (op)
                     store_f32<NT>(bounded(op + (int64_t)(n0 + u) * ostep, 1, a.vol,
-                                          a.vol + (int64_t)a.N * a.R * W),
+                                          a.vol + (int64_t)a.N * a.vol_plane),
                                   d);
             }
         }
@@ -1018,7 +1021,7 @@ __device__ __forceinline__ void fwd_edge_wave(const FwdArgs<TIn> &a, int64_t e) 
     const int x = edge_col(rg, W, (int)(e - 6 * (e / 6)));
     if (x < 0) return;
     const int lane = (int)threadIdx.x & 63;
-    const int64_t ostep = (int64_t)a.R * W;
+    const int64_t ostep = a.vol_plane;
     const TIn *rp = a.in + (int64_t)r * a.in_row;
     float *op = a.vol ? a.vol + (int64_t)r * W + x : nullptr;
     double acc = 0.0;
@@ -1179,6 +1182,7 @@ __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL, 
         a.tau_wg = 0;
         a.pace_cap = 0;
         a.edge_wg = jb.edge_blocks;
+        a.vol_plane = (int64_t)jb.R * jb.W;
         const int64_t lt = t - jb.tile_begin;
         if constexpr (PT >= 4) {
             if (jb.vec) {

@@ -322,3 +322,34 @@ def test_invalid_arguments_raise():
         dsk.deskew(x, 30.0, 0.4, -1.0)
     with pytest.raises(ValueError):
         dsk.deskew(x.transpose(1, 2), 30.0, 0.4, 0.115)
+
+
+def test_row_bands_of_a_frame_wider_than_the_resident_tiles():
+    """1028 rows x 9 column tiles (W = 2091, edge columns) exceed the
+    workgroups an MI355X holds at once (8192 in the default shape), so the
+    paced default launch goes out as two bands of rows (516 + 512).  The
+    result equals, bit for bit, the unpaced launch of the whole frame at once,
+    and the oracle within the forward's bar."""
+    shape = (16, 1028, 2048)
+    _say(f"forward: row bands {shape}")
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 21)
+    s = oracle.shift_px(35.0, 0.4, 0.115)
+    off = oracle.offsets_uniform(shape[0], s)
+    g = st.to(DEV)
+    banded = dsk.deskew(g, 35.0, 0.4, 0.115)
+    whole = dsk.deskew(g, 35.0, 0.4, 0.115,
+                       tune={"block": 64, "per_thread": 4, "nt_store": 1, "unroll": 2,
+                             "wg_per_cu": 0, "pace_gbs": 0})
+    torch.cuda.synchronize()
+    assert banded["width"] == 2091
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(banded[k], whole[k]), k
+    sn = st.numpy()
+    ref = oracle.deskew(sn, off)
+    assert (banded["origin"], banded["width"]) == (ref["origin"], ref["width"])
+    vol = _to_np(banded["vol"])
+    _check_close(vol, ref["vol"], _interp_scale(sn, off, ref["origin"], ref["width"]), "vol")
+    _check_zero_padding(vol, ref["vol"], "vol")
+    for k in ("psum", "pmax"):
+        r = ref[k].astype(np.float64)
+        assert (np.abs(_to_np(banded[k]).astype(np.float64) - r) <= RTOL * np.abs(r)).all(), k
