@@ -500,7 +500,10 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # 10 untimed steps: the first launches after the device has idled run
+    # slower for about ten launches while its clocks ramp, which throws a
+    # paced launch off its schedule
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="target CPU time of the oracle baseline sample (0 = skip)")
     ap.add_argument("--extras",

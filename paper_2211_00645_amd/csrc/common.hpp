@@ -14,15 +14,17 @@ constexpr int64_t kMaxI32 = 2147483647;
 
 // Default forward launch shape: 64-thread workgroups, one 4-column group per
 // lane, non-temporal stores, 2-plane pipeline (built for 8 waves per SIMD),
-// paced at 5800 GB/s.  On the 512x512x2048 stack, back to back, the launch
+// paced at 5700 GB/s.  On the 512x512x2048 stack, back to back, the launch
 // time follows the pace (bytes / pace + about 3 us) up to the cliff:
 // 5600: 0.853 ms, 5700: 0.839, 5800: 0.824; past it the wavefronts fall
 // behind the schedule, stop sleeping and drift apart (5900: 0.823-0.840,
 // 6000: 0.91, 6100: 0.95, unpaced 1.01-1.06).  The cliff sat between 5850
-// and 6000 GB/s on the devices measured, so the default stays 100-200 GB/s
-// below it; other frames put it elsewhere (5400-6000 GB/s), and
+// and 6000 GB/s on the devices measured, but in long runs 5800 still lost
+// some launches to it (a fifth of them at 0.85-0.94 ms, 0.845 ms on
+// average against a 0.828 ms median) where 5700 held at 0.839-0.842 ms;
+// other frames put the cliff elsewhere (5000-6000 GB/s), and
 // dsk_deskew_autotune finds it for a given frame on the device at hand.
-constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5800};
+constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
 
 // Default shape of launches without a volume (projections only, the live
 // view): a 4-plane load-ahead keeps enough reads in flight (on the

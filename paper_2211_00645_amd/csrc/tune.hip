@@ -130,7 +130,7 @@ std::vector<dsk_tune> fwd_candidates(bool paced) {
         return c;
     }
     std::vector<dsk_tune> c{kDefaultTune};
-    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5700, 5900, 6000})
+    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5800, 5900, 6000})
         c.push_back(dsk_tune{64, 4, 1, 2, 0, pace});
     // a 4-plane pipeline keeps more reads in flight where tiles are few (a
     // float32 stack of 256 x 512 x 1024 into 1793 columns: 0.308 ms at 5400
@@ -217,10 +217,11 @@ size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &scor
 // follow, on some devices for every launch, on others for some launches
 // only (on the 512x2048 frame, 6000 GB/s: 0.827 ms in the tuner's runs and
 // 0.90-0.97 ms after; 5900 GB/s: 0.839 ms on two devices, on a third a
-// third of its launches at 0.93-0.98 ms; 5800 held on every device
-// measured, 0.824 ms back to back).  Falling off costs 10-15%, the step
-// about 1.5%; the cap keeps the pick at or below the pace that held
-// everywhere.
+// third of its launches at 0.93-0.98 ms; 5800 held in back-to-back runs
+// on every device measured, 0.824 ms, but lost a fifth of the launches of
+// longer timed runs to the cliff, 5700 none).  Falling off costs 10-15%,
+// the step about 1.5%; the cap keeps the pick at or below the pace that
+// held everywhere.
 constexpr int kStepDown = 100;
 constexpr int kPaceCap = kDefaultTune.pace_gbs;
 
