@@ -115,7 +115,9 @@ int dsk_plan(dsk_dims d, const double *offsets_px, double shift_px,
  * clips or zero-pads the grid on the same formula.  vol, psum and pmax may
  * each be NULL (vol NULL is the live-view case); at least one must be set.
  * One fused pass: the volume and both projections come from one read of the
- * stack. */
+ * stack.  A paced frame with a volume and more column tiles than the device
+ * holds at once goes out as bands of rows, one launch each, on `stream`
+ * (bitwise the same result). */
 int dsk_deskew_u16(const uint16_t *in, dsk_dims d, dsk_geom g, float *vol,
                    float *psum, float *pmax, int64_t out_width,
                    hipStream_t stream);
