@@ -115,8 +115,8 @@ namespace {
 // Shapes the single-stack tuner times.  With a volume: one 4-column group
 // per lane with a 2- or 4-plane pipeline, and two groups per lane, each
 // unpaced and paced over the range where the cliff lies on the frames
-// measured (5000-6000 GB/s; one group per lane in 100 GB/s steps from 5400,
-// where most frames put it); the default shape is always a candidate.
+// measured (5000-6000 GB/s; one group per lane, 2-plane pipeline, in
+// 100 GB/s steps); the default shape is always a candidate.
 // Without a volume nothing is paced: groups and pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
     if (!paced) {
@@ -129,8 +129,11 @@ std::vector<dsk_tune> fwd_candidates(bool paced) {
         for (int u : {2, 4}) c.push_back(dsk_tune{64, 8, 1, u, 0, 0});
         return c;
     }
+    // every 100 GB/s from 5000 (the step-down below then lands exactly 100
+    // under the best pace: the float32 256 x 512 x 1024 frame's best, 5400,
+    // stepped down to 5200 while 5300 was missing)
     std::vector<dsk_tune> c{kDefaultTune};
-    for (int pace : {0, 5000, 5200, 5400, 5500, 5600, 5800, 5900, 6000})
+    for (int pace : {0, 5000, 5100, 5200, 5300, 5400, 5500, 5600, 5800, 5900, 6000})
         c.push_back(dsk_tune{64, 4, 1, 2, 0, pace});
     // a 4-plane pipeline keeps more reads in flight where tiles are few (a
     // float32 stack of 256 x 512 x 1024 into 1793 columns: 0.308 ms at 5400

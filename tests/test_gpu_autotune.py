@@ -16,7 +16,7 @@ from paper_2211_00645_amd import synth
 pytestmark = pytest.mark.gpu
 
 DEV = "cuda:0"
-PACES = {0, 5000, 5200, 5400, 5500, 5600, 5700, 5800, 5900, 6000, 9000, 12000}
+PACES = {0, 5000, 5100, 5200, 5300, 5400, 5500, 5600, 5700, 5800, 5900, 6000, 9000, 12000}
 
 
 def _say(msg):
