@@ -58,3 +58,23 @@ def test_two_channels_full_size():
         ref = dsk.deskew(frames[:, :, c0:c0 + 1024].contiguous(), 35.0, 0.4, 0.115, vol=False)
         torch.cuda.synchronize()
         assert torch.equal(res["psum"], ref["psum"]) and torch.equal(res["pmax"], ref["pmax"])
+
+
+def test_channels_in_row_bands():
+    """Two 2048-column channels of 1028-row frames (9 column tiles x 1028
+    rows per channel: more than the device holds at once, so each channel
+    goes out as bands of rows read in place at the frame's row pitch):
+    bitwise the dense copy's result and the unpaced whole-frame launch."""
+    frames = synth.blob_stack((8, 1028, 2 * 2048 + 8), 400, 13, device=DEV)
+    outs = dsk.deskew_channels(frames, (0, 2052), 2048, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    for c0, res in zip((0, 2052), outs):
+        dense = frames[:, :, c0:c0 + 2048].contiguous()
+        ref = dsk.deskew(dense, 35.0, 0.4, 0.115)
+        whole = dsk.deskew(dense, 35.0, 0.4, 0.115,
+                           tune={"block": 64, "per_thread": 4, "nt_store": 1, "unroll": 2,
+                                 "wg_per_cu": 0, "pace_gbs": 0})
+        torch.cuda.synchronize()
+        for k in ("vol", "psum", "pmax"):
+            assert torch.equal(res[k], ref[k]), (c0, k)
+            assert torch.equal(res[k], whole[k]), (c0, k)

@@ -353,3 +353,26 @@ def test_row_bands_of_a_frame_wider_than_the_resident_tiles():
     for k in ("psum", "pmax"):
         r = ref[k].astype(np.float64)
         assert (np.abs(_to_np(banded[k]).astype(np.float64) - r) <= RTOL * np.abs(r)).all(), k
+
+
+def test_row_bands_float32():
+    """The float32 path through the same row bands (1028 rows x 9 column
+    tiles, W = 2091): bitwise the unpaced whole-frame launch, and the
+    oracle within the forward's bar on the projections."""
+    shape = (16, 1028, 2048)
+    _say(f"forward: row bands, float32 {shape}")
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 22).to(torch.float32)
+    g = st.to(DEV)
+    banded = dsk.deskew(g, 35.0, 0.4, 0.115)
+    whole = dsk.deskew(g, 35.0, 0.4, 0.115,
+                       tune={"block": 64, "per_thread": 4, "nt_store": 1, "unroll": 2,
+                             "wg_per_cu": 0, "pace_gbs": 0})
+    torch.cuda.synchronize()
+    assert banded["width"] == 2091
+    for k in ("vol", "psum", "pmax"):
+        assert torch.equal(banded[k], whole[k]), k
+    off = oracle.offsets_uniform(shape[0], oracle.shift_px(35.0, 0.4, 0.115))
+    ref = oracle.deskew(st.numpy(), off)
+    for k in ("psum", "pmax"):
+        r = ref[k].astype(np.float64)
+        assert (np.abs(_to_np(banded[k]).astype(np.float64) - r) <= RTOL * np.abs(r)).all(), k
