@@ -28,13 +28,15 @@ constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
 
 // Default shape of launches without a volume (projections only, the live
 // view): a 4-plane load-ahead keeps enough reads in flight (on the
-// 512x512x2048 stack 0.228 ms against 0.240 for 2 planes).  They only
-// read, and are not paced by default: a pace above what the device reaches
-// only makes the wavefronts whose planes start late wait for their turn
-// instead of competing with the others at the start, which gained 1-5% on
-// that stack (9000-11000 GB/s) and lost 1-3% on wider frames (more tiles
-// than resident wavefronts); dsk_deskew_autotune tries both.
-constexpr dsk_tune kDefaultProjTune = {64, 4, 1, 4, 0, 0};
+// 512x512x2048 stack 0.228 ms against 0.240 for 2 planes), paced at 9000
+// GB/s.  They only read; a pace above what the device reaches never holds a
+// running wavefront back, it only makes the wavefronts whose plane range
+// starts late (the frame's outer column tiles) wait for their turn instead
+// of competing with the others at the start: 0.238 -> 0.219 ms on that
+// stack.  A frame with more tiles than resident workgroups is not paced
+// (fwd_launch): its second round of tiles would wait out a schedule that
+// began before they did (1-3% slower when they were).
+constexpr dsk_tune kDefaultProjTune = {64, 4, 1, 4, 0, 9000};
 
 inline const dsk_tune &default_tune(const void *vol) {
     return vol ? kDefaultTune : kDefaultProjTune;

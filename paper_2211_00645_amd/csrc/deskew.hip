@@ -127,6 +127,10 @@ static hipError_t fwd_launch(FwdArgs<TIn> a, bool vec, int64_t tiles, int64_t ed
                 cap = (int64_t)(a.vol ? vec_resident_per_cu<TIn, B, PT / 4, U, NT, true>()
                                       : vec_resident_per_cu<TIn, B, PT / 4, U, false, false>()) *
                       device_cus();
+            // without a volume a frame whose tiles do not all fit at once is
+            // not paced: its later tiles would wait out a schedule that began
+            // before they started
+            if (!a.vol && pace_gbs > 0 && tiles * a.R > cap) pace_gbs = 0;
             auto launch_rows = [&](FwdArgs<TIn> f, int64_t f_edge) {
                 if (pace_gbs > 0) {
                     // one tile's share of a plane's bytes, timed at pace_gbs

@@ -120,10 +120,10 @@ namespace {
 // Without a volume nothing is paced: groups and pipeline depth only.
 std::vector<dsk_tune> fwd_candidates(bool paced) {
     if (!paced) {
-        // without a volume: the default (unpaced), its shape at 9000 and
-        // 12000, a 2-plane pipeline unpaced and at 9000, two groups per
-        // lane unpaced
-        std::vector<dsk_tune> c{kDefaultProjTune, dsk_tune{64, 4, 1, 4, 0, 9000},
+        // without a volume: the default (paced at 9000), its shape unpaced
+        // and at 12000, a 2-plane pipeline unpaced and at 9000, two groups
+        // per lane unpaced
+        std::vector<dsk_tune> c{kDefaultProjTune, dsk_tune{64, 4, 1, 4, 0, 0},
                                 dsk_tune{64, 4, 1, 4, 0, 12000}, dsk_tune{64, 4, 1, 2, 0, 0},
                                 dsk_tune{64, 4, 1, 2, 0, 9000}};
         for (int u : {2, 4}) c.push_back(dsk_tune{64, 8, 1, u, 0, 0});
