@@ -376,3 +376,22 @@ def test_row_bands_float32():
     for k in ("psum", "pmax"):
         r = ref[k].astype(np.float64)
         assert (np.abs(_to_np(banded[k]).astype(np.float64) - r) <= RTOL * np.abs(r)).all(), k
+
+
+def test_projections_only_wider_than_the_resident_tiles():
+    """Without a volume (the live view) a frame whose tiles do not all fit at
+    once (1028 rows x 9 tiles) is launched unpaced even in the paced default
+    shape: projections bitwise those of the explicitly unpaced launch and of
+    the fused pass with the volume (which goes out as row bands)."""
+    shape = (16, 1028, 2048)
+    _say(f"forward: projections only, more tiles than resident {shape}")
+    g = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 23, device=DEV)
+    banded = dsk.deskew(g, 35.0, 0.4, 0.115, vol=False)
+    whole = dsk.deskew(g, 35.0, 0.4, 0.115, vol=False,
+                       tune={"block": 64, "per_thread": 4, "nt_store": 1, "unroll": 4,
+                             "wg_per_cu": 0, "pace_gbs": 0})
+    full = dsk.deskew(g, 35.0, 0.4, 0.115)
+    torch.cuda.synchronize()
+    for k in ("psum", "pmax"):
+        assert torch.equal(banded[k], whole[k]), k
+        assert torch.equal(banded[k], full[k]), k
