@@ -170,7 +170,7 @@ int dsk_deskew_offsets_tuned(const void *in, int in_is_f32, dsk_dims d,
  * in longer back-to-back runs, on the caller's own buffers and stream, and
  * returns in *tune, among the shapes whose mean time per launch is within
  * 0.5% of the fastest, the one paced slowest; with a volume its pace then
- * steps down by at least 100 GB/s and to at most the default's 5700, clear
+ * steps down by at least 100 GB/s and to at most 5800, clear
  * of the pacing cliff (*ms, host, may be NULL: the mean time measured for
  * the returned shape).  Arguments as
  * dsk_deskew_offsets_tuned.  Every trial computes the full result, so the

@@ -207,19 +207,22 @@ int launch_forward_layout(const void *in, int in_is_f32, dsk_dims d, const InLay
         lay.hi < last + d.cols)
         return DSK_ESHAPE;
     const bool vec = vec_ok(t, d, width, in, in_is_f32, vol, lay.plane);
-    const int64_t tiles = tiles_x(width, t, vec);
+    // volume rows' tiles on 128-byte boundaries when the plane pitch keeps
+    // them there in every plane
+    const bool align = vec && vol && ((int64_t)d.rows * width) % 32 == 0;
+    const int64_t tiles = tiles_x(width, t, vec, align ? 7 : 0);
     const int64_t edge = edge_blocks(d, width, t, vec, vol != nullptr);
     if (tiles * (int64_t)d.rows + edge > kMaxI32) return DSK_ESHAPE;
     hipError_t e;
     if (in_is_f32) {
         FwdArgs<float> a{(const float *)in, vol, psum, pmax, offs, shift, (double)origin,
                          width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                         0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width};
+                         0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width, align ? 1 : 0};
         e = fwd_dispatch<float>(a, t, vec, tiles, edge, stream);
     } else {
         FwdArgs<uint16_t> a{(const uint16_t *)in, vol, psum, pmax, offs, shift, (double)origin,
                             width, d.planes, d.rows, d.cols, lay.row, lay.plane, lay.lo, lay.hi,
-                            0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width};
+                            0u, 0u, 0, (int32_t)edge, (int64_t)d.rows * width, align ? 1 : 0};
         e = fwd_dispatch<uint16_t>(a, t, vec, tiles, edge, stream);
     }
     return hip_status(e);

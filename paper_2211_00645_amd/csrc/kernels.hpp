@@ -179,6 +179,10 @@ struct FwdArgs {
     // launch covers a band of its rows (vol, psum and pmax then point at the
     // band's first row).
     int64_t vol_plane;
+    // Vector launches with a volume whose plane pitch is a multiple of 32
+    // floats: every row's tiles start on a 128-byte boundary of the volume
+    // (the host adds a tile's worth of room: 7 groups per row).
+    int32_t align_tiles;
 };
 
 // Plane pacing: a wavefront that reaches plane n before t0 + n * tau sleeps
@@ -434,7 +438,19 @@ struct VecTile {
         ostep = a.vol_plane;
         wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
         lane = (int)threadIdx.x & 63;
-        const int base = tile * BLOCK * G;
+        int base = tile * BLOCK * G;
+        if constexpr (VOL) {
+            // shift the row's tile grid back by the groups that lie between
+            // the previous 128-byte boundary of the volume and the row's
+            // first group, so that each wavefront's 1 KB stores of a plane
+            // cover 8 whole cache lines (a store run straddling lines leaves
+            // partial lines that its neighbour completes much later, and the
+            // launch then falls off its pacing schedule at paces that
+            // line-aligned rows hold); the plane pitch being a multiple of 32
+            // floats, the shift is the same in every plane
+            if (a.align_tiles)
+                base -= (int)((((uintptr_t)(a.vol + (int64_t)r * W + ca) >> 2) & 31) >> 2);
+        }
         alive = base + (VOL ? 64 : 64 * G) * wv < ng;
         // the plane pitch is a multiple of 4, so every plane's row start has
         // this residue
@@ -465,10 +481,12 @@ struct VecTile {
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if constexpr (VOL) {
+                // lanes before the row's first group (an aligned tile grid)
+                // repeat it, as lanes past the last repeat the last
                 const int w0 = base + 64 * wv + BLOCK * g;
-                gi[g] = min(base + (int)threadIdx.x + BLOCK * g, ng - 1);
-                gfirst[g] = min(w0, ng - 1);
-                glast[g] = min(w0 + 63, ng - 1);
+                gi[g] = max(0, min(base + (int)threadIdx.x + BLOCK * g, ng - 1));
+                gfirst[g] = max(0, min(w0, ng - 1));
+                glast[g] = max(0, min(w0 + 63, ng - 1));
             } else {
                 const int w0 = base + 64 * G * wv + g;
                 gi[g] = min(w0 + G * lane, ng - 1);
@@ -1183,6 +1201,7 @@ __global__ __launch_bounds__(BLOCK, vec_waves_per_eu(PT >= 8 ? 2 : 1, UNR, VOL, 
         a.pace_cap = 0;
         a.edge_wg = jb.edge_blocks;
         a.vol_plane = (int64_t)jb.R * jb.W;
+        a.align_tiles = 0;
         const int64_t lt = t - jb.tile_begin;
         if constexpr (PT >= 4) {
             if (jb.vec) {

@@ -226,7 +226,11 @@ size_t choose(const std::vector<dsk_tune> &cand, const std::vector<double> &scor
 // the step about 1.5%; the cap keeps the pick at or below the pace that
 // held everywhere.
 constexpr int kStepDown = 100;
-constexpr int kPaceCap = kDefaultTune.pace_gbs;
+// 5800 held the 512 x 512 x 2048 frame's long timed runs once each row's
+// tiles start on 128-byte boundaries (at most 1 of 40 launches a few us
+// behind; 6000 lost a third of them); the default stays at 5700, which
+// holds on more frames
+constexpr int kPaceCap = 5800;
 
 size_t step_down(const std::vector<dsk_tune> &cand, const dsk_tune &t) {
     size_t pick = cand.size();

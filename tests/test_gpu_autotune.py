@@ -36,7 +36,7 @@ def test_tuned_shape_gives_the_default_result(shape, angle, step):
     got = dsk.autotune(st, angle, step, 0.115, reps=3)
     assert _valid(got["tune"]) and got["ms"] > 0.0
     # with a volume the pick is stepped down to at most the default's pace
-    assert got["tune"]["pace_gbs"] <= 5700
+    assert got["tune"]["pace_gbs"] <= 5800
     ref = dsk.deskew(st, angle, step, 0.115)
     res = dsk.deskew(st, angle, step, 0.115, tune=got["tune"])
     auto = dsk.deskew(st, angle, step, 0.115, tune="auto")
