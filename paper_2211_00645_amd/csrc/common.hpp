@@ -73,13 +73,11 @@ inline bool vec_ok(const dsk_tune &t, dsk_dims d, int64_t width, const void *in,
 }
 
 // Column tiles of one output row.  The vector kernel tiles the row's whole
-// 4-aligned groups (at most W/4 of them, plus extra_groups of room when its
-// tile grid is shifted onto 128-byte boundaries); the scalar kernel tiles
-// columns.
-inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec, int extra_groups = 0) {
+// 4-aligned groups (at most W/4 of them); the scalar kernel tiles columns.
+inline int64_t tiles_x(int64_t width, const dsk_tune &t, bool vec) {
     const int64_t tile = (int64_t)t.block * t.per_thread;
     if (vec) {
-        const int64_t groups = width / 4 + extra_groups, per = tile / 4;
+        const int64_t groups = width / 4, per = tile / 4;
         const int64_t n = (groups + per - 1) / per;
         return n > 0 ? n : 1;
     }

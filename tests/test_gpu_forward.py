@@ -135,6 +135,33 @@ def test_misaligned_buffers_match_aligned(cfg1):
     assert torch.equal(vm, base["vol"])
 
 
+@pytest.mark.parametrize("width,lead", [(1256, 0), (1272, 0), (1276, 0), (1280, 0), (1280, 4),
+                                        (1112, 12)])
+def test_aligned_tile_grids_match_the_scalar_kernel(width, lead):
+    """Volumes whose rows the vector kernel tiles on 128-byte boundaries
+    (rows*W a multiple of 32), with the shifted grids fitting the row's tiles
+    (1256: shifts 0-6 groups, 58 + 6 of 64 in the last tile; 1280) and not
+    (1272, 1276: the plain grid is kept), the volume starting on a 128-byte
+    boundary or lead floats after one: bitwise the scalar kernel's result
+    (a volume 4 bytes off alignment)."""
+    shape = (8, 32, 1024)
+    _say(f"forward: aligned tile grids W {width} lead {lead}")
+    st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 23)
+    g = st.to(DEV)
+    n, r = shape[0], shape[1]
+    vflat = torch.full((n * r * width + 16,), -1.0, device=DEV)
+    assert vflat.data_ptr() % 128 == 0
+    va = vflat[lead:lead + n * r * width].view(n, r, width)
+    sflat = torch.full((n * r * width + 1,), -1.0, device=DEV)
+    vs = sflat[1:].view(n, r, width)
+    a = dsk.deskew(g, 35.0, 0.4, 0.115, width=width, out={"vol": va})
+    b = dsk.deskew(g, 35.0, 0.4, 0.115, width=width, out={"vol": vs})
+    torch.cuda.synchronize()
+    assert torch.equal(va, vs)
+    for k in ("psum", "pmax"):
+        assert torch.equal(a[k], b[k]), k
+
+
 def test_determinism(cfg1):
     st, _ = cfg1
     x = st.to(DEV)
