@@ -17,13 +17,12 @@ constexpr int64_t kMaxI32 = 2147483647;
 // paced at 5700 GB/s.  On the 512x512x2048 stack, back to back, the launch
 // time follows the pace (bytes / pace + about 3 us) up to the cliff:
 // 5600: 0.853 ms, 5700: 0.839, 5800: 0.824; past it the wavefronts fall
-// behind the schedule, stop sleeping and drift apart (5900: 0.823-0.840,
-// 6000: 0.91, 6100: 0.95, unpaced 1.01-1.06).  The cliff sat between 5850
-// and 6000 GB/s on the devices measured, but in long runs 5800 still lost
-// some launches to it (a fifth of them at 0.85-0.94 ms, 0.845 ms on
-// average against a 0.828 ms median) where 5700 held at 0.839-0.842 ms;
-// other frames put the cliff elsewhere (5000-6000 GB/s), and
-// dsk_deskew_autotune finds it for a given frame on the device at hand.
+// behind the schedule, stop sleeping and drift apart (unpaced 1.01-1.06
+// ms).  With each row's tiles on 128-byte boundaries of the volume that
+// frame holds 5800 (0.828 ms over the timed runs) and its cliff lies past
+// 5900, but other frames put it anywhere between 5000 and 6000 GB/s, so
+// the default keeps a step of margin and dsk_deskew_autotune finds the
+// cliff of a given frame on the device at hand.
 constexpr dsk_tune kDefaultTune = {64, 4, 1, 2, 0, 5700};
 
 // Default shape of launches without a volume (projections only, the live
