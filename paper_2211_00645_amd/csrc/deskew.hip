@@ -380,9 +380,8 @@ int launch_backward(const float *in, const float *gvol, dsk_dims d, const double
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return DSK_EHIP;
     if (goff) {
-        const int fb = 64;
-        hipLaunchKernelGGL(k_backward_finalize<0>, dim3((d.planes + fb - 1) / fb), dim3(fb), 0,
-                           stream, (const double *)ws, d.planes, G, goff);
+        hipLaunchKernelGGL(k_backward_finalize<0>, dim3((unsigned)d.planes), dim3(64), 0, stream,
+                           (const double *)ws, d.planes, G, goff);
         e = hipGetLastError();
     }
     return hip_status(e);

@@ -1320,16 +1320,22 @@ __global__ __launch_bounds__(BLOCK) void k_backward(BwdArgs a) {
     }
 }
 
-// Fixed-order sum of the G partials of each plane.
+// Fixed-order sum of the G partials of each plane, one wavefront per plane
+// (blockIdx.x = plane, 64 threads): lane l adds partials l, l + 64, ... in
+// turn (adjacent lanes read adjacent partials), then the 64 lane sums are
+// halved pairwise (lane l + o into lane l for o = 32, 16, ..., 1), so the
+// order of the additions is the same in every call.
 template <int UNUSED = 0>
-__global__ void k_backward_finalize(const double *__restrict__ partial, int N, int G,
-                                    double *__restrict__ gout) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n < N) {
-        double s = 0.0;
-        for (int g = 0; g < G; ++g) s += partial[(int64_t)n * G + g];
-        gout[n] = s;
-    }
+__global__ void __launch_bounds__(64) k_backward_finalize(const double *__restrict__ partial,
+                                                          int N, int G,
+                                                          double *__restrict__ gout) {
+    const int n = blockIdx.x, l = threadIdx.x;
+    if (n >= N) return;
+    const double *p = partial + (int64_t)n * G;
+    double s = 0.0;
+    for (int g = l; g < G; g += 64) s += p[g];
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+    if (l == 0) gout[n] = s;
 }
 
 // ---------------------------------------------------------------- rolling
