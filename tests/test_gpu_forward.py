@@ -138,12 +138,14 @@ def test_misaligned_buffers_match_aligned(cfg1):
 @pytest.mark.parametrize("width,lead", [(1256, 0), (1272, 0), (1276, 0), (1280, 0), (1280, 4),
                                         (1112, 12)])
 def test_aligned_tile_grids_match_the_scalar_kernel(width, lead):
-    """Volumes whose rows the vector kernel tiles on 128-byte boundaries
-    (rows*W a multiple of 32), with the shifted grids fitting the row's tiles
-    (1256: shifts 0-6 groups, 58 + 6 of 64 in the last tile; 1280) and not
-    (1272, 1276: the plain grid is kept), the volume starting on a 128-byte
-    boundary or lead floats after one: bitwise the scalar kernel's result
-    (a volume 4 bytes off alignment)."""
+    """Frames with rows*W a multiple of 32, where the vector kernel starts
+    each row's tiles on a 128-byte boundary of the volume if the shifted
+    grids fit the row's tiles: they fit for 1256 (shifts 0-6 groups, 58 + 6
+    of the last tile's 64), 1280 on a boundary (no shift) and 1112 twelve
+    floats after one (shifts up to 7, 22 + 7 of 64); they do not for 1272,
+    1276 and 1280 four floats after a boundary (shift 1, 64 + 1), which keep
+    the plain grid.  Each is bitwise the scalar kernel's result (a volume 4
+    bytes off alignment)."""
     shape = (8, 32, 1024)
     _say(f"forward: aligned tile grids W {width} lead {lead}")
     st = synth.blob_stack(shape, synth.blobs_for_volume(*shape), 23)
